@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against results that do not come from the oracle itself.
+
+Each test names what it pins:
+  - Philox4x32-10 against the header implementations shipped with PyTorch and
+    rocRAND (library routines, compiled here from their header source);
+  - thresholds of Eq. (8) against a 50-digit evaluation of exp;
+  - Gibbs averages of Eqs. (4)-(5) by exact enumeration of all 2^N states;
+  - the Markov chain of Eq. (6) as explicit transition matrices (detailed
+    balance, stationarity, sampled one-sweep frequencies);
+  - incremental energy/magnetisation bookkeeping against a full recount;
+  - the H -> -H symmetry of Eq. (3);
+  - the T -> 0 ground state argument of Section 5;
+  - disorder at high T;
+  - the square-lattice special case (Onsager/Yang closed forms);
+  - an isolated spin (tanh(H/T));
+  - independence of the order of sites inside a sublattice;
+  - Eq. (2) against the printed Table 1.
+"""
+
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import cpu, physics, ref
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------- Philox
+def _random_counters(n, seed=7):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, 2**32, size=(n, 6), dtype=np.uint64).tolist()
+    rows += [[0] * 6, [0xFFFFFFFF] * 6, [1, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0xFFFFFFFF, 0]]
+    return rows
+
+
+_TORCH_PROG = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  while (scanf("%x %x %x %x %x %x", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    at::philox_engine e((uint64_t)k0 | ((uint64_t)k1 << 32), (uint64_t)c2 | ((uint64_t)c3 << 32), 0);
+    e.set_offset((uint64_t)c0 | ((uint64_t)c1 << 32));
+    unsigned a = e(), b = e(), c = e(), d = e();
+    printf("%08x %08x %08x %08x\n", a, b, c, d);
+  }
+}
+"""
+
+_ROCRAND_PROG = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+struct probe : rocrand_device::philox4x32_10_engine {
+  uint4 raw(uint4 c, uint2 k) { return ten_rounds(c, k); }
+};
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  probe p;
+  while (scanf("%x %x %x %x %x %x", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    uint4 r = p.raw(uint4{c0, c1, c2, c3}, uint2{k0, k1});
+    printf("%08x %08x %08x %08x\n", r.x, r.y, r.z, r.w);
+  }
+}
+"""
+
+
+def _run_prog(exe, rows):
+    inp = "".join("%x %x %x %x %x %x\n" % tuple(r) for r in rows)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return [[int(w, 16) for w in line.split()] for line in out.strip().splitlines()]
+
+
+def _check_against(rows, got):
+    assert len(got) == len(rows)
+    for r, g in zip(rows, got):
+        ctr, key = r[:4], r[4:]
+        assert cpu.philox(ctr, key) == g, r
+        assert ref.philox4x32_10(ctr, key) == g, r
+
+
+def test_philox_matches_torch_header(oracle_lib, tmp_path):
+    import torch
+
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    src = tmp_path / "p.cpp"
+    src.write_text(_TORCH_PROG)
+    exe = str(tmp_path / "p")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I" + inc, str(src), "-o", exe], check=True)
+    rows = _random_counters(300)
+    _check_against(rows, _run_prog(exe, rows))
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand_header(oracle_lib, tmp_path):
+    src = tmp_path / "r.cpp"
+    src.write_text(_ROCRAND_PROG)
+    exe = str(tmp_path / "r")
+    subprocess.run(["hipcc", "-std=c++17", "-O1", "-x", "hip", "--offload-arch=gfx950", str(src), "-o", exe],
+                   check=True, capture_output=True)
+    rows = _random_counters(300, seed=11)
+    _check_against(rows, _run_prog(exe, rows))
+
+
+# --------------------------------------------------------------------------- thresholds
+def test_thresholds_against_high_precision_exp(oracle_lib):
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    for T in (1e-3, 0.5, 1.0, 2.269, 3.0, 4.0, 7.3, 12.0, 1e6):
+        for h_num in (-241, -120, -7, 0, 1, 55, 100, 120, 241):
+            tab = cpu.threshold_table(T, h_num)
+            for si, s in enumerate((-1, 1)):
+                for n in range(-12, 13):
+                    q = s * (20 * n + h_num)
+                    thr = int(tab[si, n + 12])
+                    if q <= 0:
+                        assert thr == 0xFFFFFFFF
+                        continue
+                    exact = mpmath.exp(-mpmath.mpf(q) / 10 / T) * 2**32
+                    # floor of a double within 1 ulp of exact: off by at most one count
+                    assert abs(thr - int(mpmath.floor(exact))) <= 1, (T, h_num, s, n)
+                    assert thr <= 2**32 - 430
+    # monotone in q at fixed T
+    vals = [cpu.lib().orc_threshold(q, 2.5) for q in range(1, 500)]
+    assert all(a >= b for a, b in zip(vals, vals[1:]))
+    # T -> 0: every uphill move is rejected
+    assert all(cpu.lib().orc_threshold(q, 1e-3) == 0 for q in range(1, 200))
+
+
+# --------------------------------------------------------------------------- exact enumeration
+def _tiny_films():
+    h8 = np.ones((4, 4), dtype=np.uint8)                    # square lattice, 8 sites
+    h16 = np.full((4, 4), 2, dtype=np.uint8)                # two layers, 16 sites
+    rng = np.random.default_rng(3)
+    while True:                                             # three layers, <= 20 sites
+        h20 = rng.integers(0, 4, size=(4, 4)).astype(np.uint8)
+        n = ref.TinyFilm(h20, 3).N
+        if 14 <= n <= 20:
+            break
+    return [(h8, 1), (h16, 2), (h20, 3)]
+
+
+# h_num is kept off multiples of 20: then q = s (20 n + h_num) is never 0, no
+# move is accepted deterministically at dE = 0, and the sweep chain is ergodic
+# (checked on the 8-site film by its spectral gap below).  Temperatures and
+# fields are chosen so that the chain tunnels between +M and -M often enough
+# for block means to see both (the 16-site film has coordination 8).
+@pytest.mark.parametrize("T,h_num", [(3.0, 45), (6.0, 5), (9.0, -25)])
+def test_exact_enumeration(oracle_lib, T, h_num):
+    for h, Z in _tiny_films():
+        tf = ref.TinyFilm(h, Z)
+        if tf.N <= 8:
+            w = np.sort(np.abs(np.linalg.eigvals(ref.sweep_matrix(tf, T, h_num))))[::-1]
+            assert w[0] == pytest.approx(1.0) and w[1] < 0.95
+        ex = ref.enumerate_exact(tf, T, h_num)
+        f = cpu.Film(h, Z, seed=0xC0FFEE + Z, replica=Z)
+        f.run(T, h_num, 2000)
+        nblk, blk = 40, 10000
+        m, am, e = [], [], []
+        for _ in range(nblk):
+            r = f.run(T, h_num, blk)
+            m.append(r.sum_M / blk)
+            am.append(r.sum_absM / blk)
+            e.append(r.sum_E / blk)
+        for est, key in ((m, "M"), (am, "absM"), (e, "E_bond")):
+            mean = float(np.mean(est))
+            se = float(np.std(est, ddof=1) / math.sqrt(nblk))
+            assert abs(mean - ex[key]) <= 5.0 * se + 1e-3, (key, Z, T, h_num, mean, ex[key], se)
+
+
+def test_zero_field_tiny_film_is_not_ergodic():
+    """At H = 0 a move with dE = 0 is always taken (Eq. 8 accepts E2 <= E1), which
+    on the 8-site torus (every site of sublattice 0 bonded to every site of
+    sublattice 1) leaves several unit eigenvalues in the sweep matrix: time
+    averages there depend on the start, so exact-enumeration pins avoid H = 0."""
+    tf = ref.TinyFilm(np.ones((4, 4), dtype=np.uint8), 1)
+    w = np.sort(np.abs(np.linalg.eigvals(ref.sweep_matrix(tf, 2.5, 0))))[::-1]
+    assert w[1] == pytest.approx(1.0)
+
+
+# --------------------------------------------------------------------------- transition matrices
+def _pair_and_triangle():
+    pair = np.zeros((4, 4), dtype=np.uint8)
+    pair[0, 0] = 1
+    pair[1, 1] = 1
+    tri = pair.copy()
+    tri[0, 1] = 2              # h(x=1, y=0) = 2 -> site (1, 0, 1)
+    return [(pair, 1), (tri, 2)]
+
+
+def test_transition_matrix_structure():
+    films = _pair_and_triangle()
+    pf = ref.TinyFilm(*films[0])
+    tf = ref.TinyFilm(*films[1])
+    assert pf.N == 2 and len(pf.bonds) == 1 and sorted(pf.sub) == [0, 1]
+    assert tf.N == 3 and len(tf.bonds) == 3 and sorted(tf.sub) == [0, 1, 2]
+    for (h, Z) in films:
+        film = ref.TinyFilm(h, Z)
+        for T, hn in ((1.5, 10), (3.0, -40), (0.7, 0)):
+            states, pi = ref.boltzmann(film, T, hn)
+            for sigma in range(4):
+                for quant, tol in ((False, 1e-15), (True, 2.0**-31)):
+                    P = ref.phase_matrix(film, T, hn, sigma, quantised=quant)
+                    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-15)
+                    flow = pi[:, None] * P
+                    assert np.max(np.abs(flow - flow.T)) <= tol
+            S = ref.sweep_matrix(film, T, hn, quantised=False)
+            assert np.max(np.abs(pi @ S - pi)) <= 1e-14
+
+
+def test_transition_frequencies_sampled(oracle_lib):
+    """One-sweep transition frequencies of the C oracle against the quantised sweep matrix."""
+    h, Z = _pair_and_triangle()[1]
+    film = ref.TinyFilm(h, Z)
+    T, hn = 1.5, 10
+    S = ref.sweep_matrix(film, T, hn, quantised=True)
+    states = [tuple(s) for s in __import__("itertools").product((-1, 1), repeat=film.N)]
+    idx = {s: a for a, s in enumerate(states)}
+    start = (1, -1, 1)
+    f = cpu.Film(h, Z, seed=99, replica=5)
+    cube = np.zeros((Z, 4, 4), dtype=np.int8)
+    for i, (x, y, z) in enumerate(film.sites):
+        cube[z, y, x] = start[i]
+    nsamp = 60000
+    counts = np.zeros(len(states))
+    for t in range(nsamp):
+        f.set_spins(cube, t)
+        f.run(T, hn, 1)
+        sp = f.spins()
+        counts[idx[tuple(int(sp[z, y, x]) for (x, y, z) in film.sites)]] += 1
+    p = S[idx[start]]
+    exp = nsamp * p
+    sd = np.sqrt(nsamp * p * (1 - p)) + 1e-9
+    assert np.all(np.abs(counts - exp) <= 5 * sd + 1), (counts, exp)
+    assert counts[p == 0].sum() == 0
+
+
+# --------------------------------------------------------------------------- bookkeeping / symmetry
+def test_incremental_equals_recount(oracle_lib):
+    from isf_workloads import config_plain_hysteresis_small
+
+    c = config_plain_hysteresis_small()
+    h = c.heights()
+    f = cpu.Film(h, c.Z, c.mc_seed, init=cpu.INIT_RANDOM)
+    assert f.state()[:2] == f.recount()
+    for hn in c.h_nums[::7]:
+        f.run(c.T, hn, 5)
+        assert f.state()[:2] == f.recount()
+    # the second implementation counts bonds independently
+    tf = ref.TinyFilm(h, c.Z)
+    sp = f.spins()
+    tf.s = [int(sp[z, y, x]) for (x, y, z) in tf.sites]
+    assert f.state()[0] == tf.magnetisation()
+    assert f.state()[1] == tf.bond_energy()
+    assert f.state()[3] == len(tf.bonds)
+    assert f.state()[2] == tf.N
+
+
+@pytest.mark.parametrize("init", [cpu.INIT_UP, cpu.INIT_RANDOM])
+def test_field_reversal_symmetry(oracle_lib, init):
+    rng = np.random.default_rng(5)
+    h = rng.integers(0, 5, size=(24, 16)).astype(np.uint8)
+    a = cpu.Film(h, 4, seed=777, replica=2, init=init)
+    b = cpu.Film(h, 4, seed=777, replica=2, init=cpu.INIT_DOWN)
+    b.set_spins(-a.spins(), 0)
+    ramp = [40, 10, -20, -60, 0, 33, -1]
+    for hn in ramp:
+        ra = a.run(2.5, hn, 3).as_tuple()
+        rb = b.run(2.5, -hn, 3).as_tuple()
+        assert np.array_equal(b.spins(), -a.spins())
+        assert rb == (-ra[0], ra[1], -ra[2], ra[3], ra[4], ra[5])
+
+
+def test_zero_temperature_ground_state(oracle_lib):
+    rng = np.random.default_rng(8)
+    h = rng.integers(0, 5, size=(32, 32)).astype(np.uint8)
+    f = cpu.Film(h, 4, seed=1, init=cpu.INIT_UP)
+    n_occ, n_bonds = f.state()[2], f.state()[3]
+    for _ in range(3):
+        r = f.run(1e-3, 1, 10)
+        assert r.M == n_occ and r.E == -n_bonds and r.accepted == 0
+    for sign in (1, -1):
+        g = cpu.Film(h, 4, seed=2, init=cpu.INIT_RANDOM)
+        assert abs(g.state()[0]) < n_occ
+        r = g.run(1e-3, 241 * sign, 1)
+        assert r.M == sign * n_occ and r.E == -n_bonds
+        r = g.run(1e-3, 241 * sign, 5)
+        assert r.M == sign * n_occ and r.accepted == 0
+
+
+def test_high_temperature_disorder(oracle_lib):
+    rng = np.random.default_rng(9)
+    h = rng.integers(0, 5, size=(64, 64)).astype(np.uint8)
+    f = cpu.Film(h, 4, seed=3, init=cpu.INIT_UP)
+    N = f.state()[2]
+    f.run(50.0, 0, 50)
+    r = f.run(50.0, 0, 1000)
+    assert abs(r.sum_M / 1000 / N) <= 5 / math.sqrt(N)
+    assert r.sum_absM / 1000 / N <= 3 / math.sqrt(N)
+
+
+def test_square_lattice_onsager(oracle_lib):
+    """Z = 1, h = 1 is the square lattice (offsets (+-1, +-1, 0)); T = 2 < Tc = 2.269."""
+    X = Y = 256
+    h = np.ones((Y, X), dtype=np.uint8)
+    T = 2.0
+    f = cpu.Film(h, 1, seed=2024, init=cpu.INIT_UP)
+    N = f.state()[2]
+    assert N == X * Y // 2 and f.state()[3] == 2 * N
+    f.run(T, 0, 300)
+    n = 2000
+    r = f.run(T, 0, n)
+    m = r.sum_absM / n / N
+    u = r.sum_E / n / N
+    assert abs(m - physics.square_lattice_magnetisation(T)) < 3e-3, m
+    assert abs(u - physics.square_lattice_energy(T)) < 3e-3, u
+    assert abs(physics.square_lattice_magnetisation(T) - 0.91132) < 1e-5
+    assert abs(physics.square_lattice_energy(T) - (-1.74556)) < 1e-5
+
+
+def test_isolated_spin(oracle_lib):
+    h = np.zeros((4, 4), dtype=np.uint8)
+    h[0, 0] = 1
+    T, hn = 1.0, 10
+    f = cpu.Film(h, 1, seed=17, init=cpu.INIT_UP)
+    assert f.state()[2] == 1 and f.state()[3] == 0
+    # exact two-state chain with the quantised threshold
+    p = cpu.lib().orc_threshold(hn, T) / 2.0**32
+    m_chain = (1 - p) / (1 + p)
+    assert abs(m_chain - physics.single_spin_magnetisation(hn / 20, T)) < 1e-9
+    nblk, blk = 50, 20000
+    ms = [f.run(T, hn, blk).sum_M / blk for _ in range(nblk)]
+    se = np.std(ms, ddof=1) / math.sqrt(nblk)
+    assert abs(np.mean(ms) - m_chain) <= 5 * se + 1e-4
+
+
+def test_site_order_independence(oracle_lib):
+    rng = np.random.default_rng(12)
+    h = rng.integers(0, 6, size=(38, 40)).astype(np.uint8)
+    films = []
+    for order in (0, 1, 2):
+        f = cpu.Film(h, 5, seed=31337, replica=9, init=cpu.INIT_RANDOM)
+        f.set_order(order)
+        films.append(f)
+    for hn in (0, 30, -45, 7):
+        recs = [f.run(3.3, hn, 4).as_tuple() for f in films]
+        assert recs[0] == recs[1] == recs[2]
+        assert np.array_equal(films[0].spins(), films[1].spins())
+        assert np.array_equal(films[0].spins(), films[2].spins())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c_oracle_matches_python_oracle(oracle_lib, seed):
+    rng = np.random.default_rng(100 + seed)
+    Y, X, Z = [(8, 8, 3), (6, 10, 4), (4, 12, 2)][seed]
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    key = int(rng.integers(0, 2**63))
+    rep = int(rng.integers(0, 1000))
+    tf = ref.TinyFilm(h, Z, seed=key, replica=rep)
+    tf.init_random()
+    cf = cpu.Film(h, Z, key, rep, init=cpu.INIT_RANDOM)
+    for T, hn in ((2.5, 20), (1.1, -7), (6.0, 0), (0.9, 55)):
+        acc = sum(tf.sweep(T, hn) for _ in range(4))
+        r = cf.run(T, hn, 4)
+        sp = cf.spins()
+        assert all(sp[z, y, x] == tf.s[i] for i, (x, y, z) in enumerate(tf.sites))
+        assert r.M == tf.magnetisation() and r.E == tf.bond_energy() and r.accepted == acc
+
+
+def test_table1_critical_concentration():
+    rows = []
+    with open(os.path.join(HERE, "golden", "table1.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    assert len(rows) == 4
+    for ml, z, tc, p, pc in rows:
+        assert round(physics.critical_concentration(z), 2) == pytest.approx(pc, abs=1e-9)
+        # single bond counting: mean-field Tc = z J lies above the printed Tc in every row
+        assert tc < z
