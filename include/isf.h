@@ -1,0 +1,243 @@
+/*
+ * isf.h -- C ABI of the MI355X (gfx950) library for Metropolis Monte Carlo of
+ * the ferromagnetic Ising model on thin films built from a surface height map.
+ *
+ * Model (Kapitan & Nefedev, Sections 2-3 and 5):
+ *   - spins S = +-1 with k = 1 and exchange J = 1 (Section 2);
+ *   - Hamiltonian with an external field, Eq. (3), each bond counted once:
+ *       E = E_bond - H M,  E_bond = -sum_<ij> S_i S_j,  M = sum_i S_i;
+ *   - 12-neighbour lattice built from an image, rows x columns x layers
+ *     (Sections 2-3).  Here: FCC in cubic-index form, sites (x, y, z) with
+ *     x+y+z even, neighbours the 12 permutations of (+-1, +-1, 0), periodic
+ *     in x and y, open in z; site occupied iff z < h[y][x];
+ *   - Metropolis acceptance, Eq. (8) with steps 1-3 of Section 5.  The field
+ *     is an integer h_num with H = h_num / 20, so the energy change of a flip
+ *     is q / 10 with q = S_i (20 n_i + h_num), n_i the sum of the neighbour
+ *     spins (vacancies count 0).  q <= 0 is always accepted; q > 0 is accepted
+ *     iff u < floor(2^32 exp(-(q/10)/T)), computed on the host in IEEE double;
+ *   - the uniform draw u of site (x, y, z) in sweep t is word (k mod 4) of
+ *     Philox4x32-10 (Salmon et al., SC 2011) with key (seed mod 2^32,
+ *     seed div 2^32) and counter (k div 4, t mod 2^32, replica, sigma), where
+ *     k = (z Y + y)(X/2) + x div 2 and sigma = (y mod 2) + 2 (z mod 2);
+ *     the random start uses counter word 3 = sigma + 4 and t = 0, and a site
+ *     starts up iff its draw is < 2^31;
+ *   - one sweep updates the four sublattices sigma = 0, 1, 2, 3 in turn
+ *     (no two neighbours are in one sublattice, so all sites of one
+ *     sublattice are updated at once); the sweep counter t counts sweeps
+ *     from 0 over the life of the lattice;
+ *   - a temperature or field step is a fixed number of sweeps (Section 3:
+ *     each step of temperature or field gets a finite number of MC steps).
+ *
+ * Every trajectory is therefore integer and reproducible bit for bit: it does
+ * not depend on the storage format, tiling, batch position or device.
+ *
+ * Memory: the caller allocates two device buffers per lattice (spin_bytes and
+ * aux_bytes from isf_lattice_bytes) and keeps them alive until
+ * isf_lattice_destroy.  The library owns only the host-side handle.  Work is
+ * enqueued on the caller's HIP stream.
+ *
+ * Errors: every function returns ISF_OK (0) or a negative code; the text of
+ * the last error of the calling thread is returned by isf_last_error().  No
+ * C++ exception crosses this interface.  A handle must not be used by two
+ * threads at once; different handles are independent.
+ */
+#ifndef ISF_H
+#define ISF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISF_ABI_VERSION 1
+
+enum {
+    ISF_OK = 0,
+    ISF_EINVAL = -1,  /* invalid argument (shape, temperature, field, pointer) */
+    ISF_ENOSPC = -2,  /* a caller buffer is smaller than isf_lattice_bytes says */
+    ISF_EHIP = -3,    /* HIP runtime error; details in isf_last_error() */
+    ISF_ESTATE = -4   /* handle in the wrong state (destroyed, busy, format) */
+};
+
+enum { ISF_FORMAT_INT8 = 0, ISF_FORMAT_BITPACK = 1 };
+enum { ISF_INIT_UP = 0, ISF_INIT_DOWN = 1, ISF_INIT_RANDOM = 2 };
+
+/* Film description.  X: image width (columns), Y: image height (rows),
+ * Z: number of atomic layers (Section 3).
+ *   INT8:    X a multiple of 8, X >= 8; Y even, Y >= 4; 1 <= Z <= 64.
+ *   BITPACK: X a multiple of 64; same Y and Z limits.
+ *   X * Y * Z / 2 <= 2^34 (stored sites). */
+typedef struct {
+    uint32_t X, Y, Z;
+    uint32_t replica;   /* Philox counter word 2 */
+    uint64_t seed;      /* Philox key */
+    uint32_t format;    /* ISF_FORMAT_* */
+    uint32_t reserved;  /* must be 0 */
+} isf_desc;
+
+/* Record of one step (a run of sweeps at fixed T and field).  Sums run over
+ * the kept sweeps (after the discarded ones), each term taken after the
+ * sweep's last sublattice. */
+typedef struct {
+    int64_t M;          /* magnetisation after the step's last sweep */
+    int64_t E;          /* E_bond after the step's last sweep */
+    int64_t sum_M;
+    int64_t sum_absM;
+    int64_t sum_E;
+    int64_t accepted;   /* accepted flips in the kept sweeps */
+} isf_record;
+
+/* One step of a schedule. */
+typedef struct {
+    double T;           /* temperature, 0 < T <= 1e6 */
+    int32_t h_num;      /* field H = h_num / 20, |h_num| <= 200000 */
+    uint32_t n_sweeps;  /* >= 1 */
+    uint32_t n_discard; /* <= n_sweeps; sweeps not summed into the record */
+    uint32_t reserved;  /* must be 0 */
+} isf_step;
+
+typedef struct {
+    int64_t M;
+    int64_t E;          /* E_bond */
+    int64_t n_occ;      /* occupied sites */
+    int64_t n_bonds;    /* bonds between occupied sites */
+    uint64_t sweeps;    /* sweep counter t */
+} isf_obs;
+
+/* Launch shape of the sweep kernels.  Every shape gives the same trajectory. */
+typedef struct {
+    uint32_t tile_x;    /* dwords (4 sites) per block row: 16, 32 or 64 */
+    uint32_t tile_y;    /* active rows per block: tile_x * tile_y = 256 */
+    uint32_t rows_per_thread; /* 1, 2 or 4 */
+    uint32_t use_graph; /* 1: replay schedules as HIP graphs, 0: plain launches */
+} isf_tuning;
+
+typedef struct isf_lattice isf_lattice;
+
+int32_t isf_abi_version(void);
+
+/* Thread-local text of the last non-zero status of this thread ("" if none). */
+const char *isf_last_error(void);
+
+/* Device-buffer sizes for a film.  Writes *spin_bytes and *aux_bytes.
+ * EINVAL if the description breaks the limits above or a pointer is null. */
+int32_t isf_lattice_bytes(const isf_desc *d, uint64_t *spin_bytes, uint64_t *aux_bytes);
+
+/* Build a film from the height map h_host[Y][X] (uint8, each 0 <= h <= Z;
+ * copied, the caller keeps ownership) into the caller's device buffers
+ * spin_dev (>= spin_bytes) and aux_dev (>= aux_bytes), set the start
+ * (ISF_INIT_*), count occupied sites and bonds, and return a handle in *out.
+ * stream is a hipStream_t (NULL = default stream).  Synchronises the stream
+ * before returning.  EINVAL / ENOSPC / EHIP as described above. */
+int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t init,
+                           void *spin_dev, uint64_t spin_bytes, void *aux_dev, uint64_t aux_bytes,
+                           void *stream, isf_lattice **out);
+
+/* Release the host handle.  Device buffers stay the caller's. */
+int32_t isf_lattice_destroy(isf_lattice *lat);
+
+/* Run a schedule of n_steps steps (each: T, field, sweeps, discarded sweeps)
+ * and write one record per step into out[n_steps] (host memory).  Enqueues on
+ * the lattice's stream and synchronises before writing out. */
+int32_t isf_run_schedule(isf_lattice *lat, const isf_step *steps, uint32_t n_steps, isf_record *out);
+
+/* n_sweeps sweeps at fixed (T, H = h_num/20); sums over the last
+ * n_sweeps - n_discard sweeps.  n_sweeps = 0 returns the current state with
+ * zero sums. */
+int32_t isf_run_sweeps(isf_lattice *lat, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_discard,
+                       isf_record *out);
+
+/* Field ramp at fixed T (Fig. 5 of the paper: hysteresis): step i runs
+ * sweeps_per_step sweeps at H = h_num[i]/20; out[n_steps]. */
+int32_t isf_ramp_field(isf_lattice *lat, double T, const int32_t *h_num, uint32_t n_steps,
+                       uint32_t sweeps_per_step, isf_record *out);
+
+/* Temperature scan at fixed field (Fig. 3: M(T)); out[n_T]. */
+int32_t isf_temperature_scan(isf_lattice *lat, const double *T, uint32_t n_T, int32_t h_num,
+                             uint32_t sweeps_per_T, uint32_t discard_per_T, isf_record *out);
+
+/* Current magnetisation, bond energy, counts and sweep counter. */
+int32_t isf_read_observables(isf_lattice *lat, isf_obs *out);
+
+/* Snapshot into cube_host[Z][Y][X] (int8): +-1 on occupied sites, 0 on
+ * vacancies and on non-sites (x+y+z odd). */
+int32_t isf_read_spins(isf_lattice *lat, int8_t *cube_host);
+
+/* Restore a snapshot (same layout; occupied sites must hold +-1, other
+ * cells are ignored) and set the sweep counter: the trajectory continues
+ * exactly as if it had not been interrupted. */
+int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube_host, uint64_t sweeps);
+
+/* Acceptance thresholds for (T, h_num): out[0][n+12] for S = -1 and
+ * out[1][n+12] for S = +1, n in [-12, 12]; 0xFFFFFFFF means always accepted. */
+int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]);
+
+/* Choose the launch shape for a lattice (validated; EINVAL if unsupported). */
+int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *tuning);
+int32_t isf_get_tuning(const isf_lattice *lat, isf_tuning *tuning);
+
+/* ---------------------------------------------------------------------------
+ * Incremental execution (used by the batched and served paths).
+ *
+ * A lattice holds at most ISF_MAX_STEPS loaded steps.  isf_schedule_load
+ * uploads a schedule (thresholds, step lengths) and resets the step state;
+ * M, E_bond and the sweep counter carry on.  isf_advance enqueues up to
+ * max_sweeps further sweeps of the loaded schedule on the lattice's stream
+ * and returns without waiting; *enqueued (may be NULL) receives the number of
+ * sweeps enqueued.  isf_schedule_remaining gives the sweeps not yet enqueued.
+ * isf_schedule_records waits for the stream and copies the records of the
+ * first n steps (n <= loaded steps) to host memory. */
+#define ISF_MAX_STEPS 1024
+
+int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n_steps);
+int32_t isf_advance(isf_lattice *lat, uint32_t max_sweeps, uint64_t *enqueued);
+int32_t isf_schedule_remaining(const isf_lattice *lat, uint64_t *sweeps);
+int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
+
+/* Batched execution: many lattices (replicas of uneven size, each with its
+ * own temperature and field schedule) advanced together.  In
+ * ISF_BATCH_PHASE_LAUNCH mode one kernel launch per sublattice covers every
+ * lattice; in ISF_BATCH_PERSISTENT mode one cooperative launch runs a whole
+ * chunk of sweeps for all lattices, with a grid-wide barrier between
+ * sublattices.  Each lattice's trajectory is identical to running it alone.
+ *
+ * A batch context owns a pinned host staging area for its launch table and
+ * uses the caller's device workspace (isf_batch_workspace_bytes) for the
+ * table on the device.  All lattices of a batch must have the same format
+ * and be idle on their own streams; the batch's work runs on the batch
+ * stream.  isf_batch_advance advances every lattice by min(max_sweeps, its
+ * remaining sweeps) and returns without waiting; isf_batch_sync waits. */
+enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1 };
+
+typedef struct isf_batch isf_batch;
+
+int32_t isf_batch_workspace_bytes(uint32_t max_lats, uint64_t *bytes);
+int32_t isf_batch_create(uint32_t max_lats, void *workspace_dev, uint64_t workspace_bytes, void *stream,
+                         isf_batch **out);
+int32_t isf_batch_destroy(isf_batch *b);
+int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, uint32_t max_sweeps,
+                          int32_t mode, uint64_t *sweeps_enqueued);
+int32_t isf_batch_sync(isf_batch *b);
+
+/* Convenience: load each lattice's full schedule (n_steps[i] <= ISF_MAX_STEPS),
+ * advance all to completion and copy out[i][n_steps[i]].  Synchronous. */
+int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, const isf_step *const *steps,
+                      const uint32_t *n_steps, isf_record *const *out, int32_t mode);
+
+/* Measurement: enqueue up to n_sweeps further sweeps of the loaded schedule
+ * as plain launches, with a pair of HIP events around every sublattice
+ * launch on the lattice's stream; waits, then writes the mean duration of
+ * the launches of sublattice s to ms_per_launch[s] (milliseconds) and the
+ * number of sweeps run to *swept.  The trajectory is the same as isf_advance. */
+int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms_per_launch[4], uint32_t *swept);
+
+/* Full recount of M and E_bond from the spins on the device (not the tracked
+ * values); used to check the incremental bookkeeping.  Synchronous. */
+int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E_bond);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISF_H */

@@ -1,0 +1,938 @@
+// C ABI of the FCC-film Ising library (declared in include/isf.h).
+//
+// Host side: validation, film construction (compact rows from the height
+// map), threshold tables of Eq. (8), schedule bookkeeping, HIP graph replay
+// and batched launch tables.  All Monte Carlo work runs in the HIP kernels of
+// isf_kernels.hip / isf_bitpack.hip / isf_persistent.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "isf.h"
+#include "isf_internal.h"
+
+namespace isf {
+hipError_t launch_phase_i8(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s);
+hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, uint32_t total_blocks,
+                                 const Tiling &tl, uint32_t sigma, hipStream_t s);
+void batch_grid_i8(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz);
+bool tiling_supported(const Tiling &tl);
+hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
+hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s);
+
+hipError_t launch_phase_bp(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s);
+hipError_t launch_phase_bp_batch(const BatchEntry *ents_dev, uint32_t n_ents, uint32_t total_blocks,
+                                 const Tiling &tl, uint32_t sigma, hipStream_t s);
+void batch_grid_bp(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz);
+bool tiling_supported_bp(const Tiling &tl);
+hipError_t launch_init_bp(const LatDev &L, int32_t mode, hipStream_t s);
+hipError_t launch_recount_bp(const LatDev &L, int64_t *out, hipStream_t s);
+
+hipError_t launch_persistent(const BatchEntry *ents_dev, uint32_t n_ents, uint32_t total_blocks, uint32_t format,
+                             const Tiling &tl, uint32_t n_sweeps, uint32_t *barrier, hipStream_t s,
+                             uint32_t *grid_used);
+}  // namespace isf
+
+using namespace isf;
+
+// ---------------------------------------------------------------------------
+// errors
+namespace {
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ISF_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                \
+    } while (0)
+
+int32_t validate_desc(const isf_desc *d) {
+    if (!d)
+        return fail(ISF_EINVAL, "null isf_desc");
+    if (d->reserved)
+        return fail(ISF_EINVAL, "isf_desc.reserved must be 0");
+    if (d->format != ISF_FORMAT_INT8 && d->format != ISF_FORMAT_BITPACK)
+        return fail(ISF_EINVAL, "unknown format %u", d->format);
+    const uint32_t xmul = d->format == ISF_FORMAT_INT8 ? 8 : 64;
+    if (d->X < xmul || d->X % xmul)
+        return fail(ISF_EINVAL, "X=%u must be a positive multiple of %u for this format", d->X, xmul);
+    if (d->Y < 4 || (d->Y & 1))
+        return fail(ISF_EINVAL, "Y=%u must be even and >= 4", d->Y);
+    if (d->Z < 1 || d->Z > 64)
+        return fail(ISF_EINVAL, "Z=%u must be in [1, 64]", d->Z);
+    const uint64_t nc = (uint64_t)d->X * d->Y * d->Z / 2;
+    if (nc > (1ull << 34))
+        return fail(ISF_EINVAL, "film too large: %llu stored sites > 2^34", (unsigned long long)nc);
+    return ISF_OK;
+}
+
+int32_t validate_T(double T) {
+    if (!std::isfinite(T) || !(T > 0.0) || T > 1e6)
+        return fail(ISF_EINVAL, "temperature %g must be finite with 0 < T <= 1e6", T);
+    return ISF_OK;
+}
+
+int32_t validate_h(int32_t h) {
+    if (h > 200000 || h < -200000)
+        return fail(ISF_EINVAL, "|h_num| = %d exceeds 200000", h);
+    return ISF_OK;
+}
+
+uint64_t spin_bytes_of(const isf_desc *d) {
+    const uint64_t W = d->X / 2;
+    if (d->format == ISF_FORMAT_INT8)
+        return (uint64_t)(d->Z + 2) * d->Y * W;
+    return (uint64_t)(d->Z + 2) * d->Y * 2 * (W / 32) * 4;
+}
+
+// Threshold of Eq. (8) for an uphill move with dE = q/10: floor(2^32 exp(-dE/T)).
+uint32_t threshold_of(int32_t q, double T) {
+    if (q <= 0)
+        return kSentinel;
+    const double p = std::exp(-((double)q / 10.0) / T);
+    return (uint32_t)std::floor(std::ldexp(p, 32));
+}
+
+void table_of(double T, int32_t h, uint32_t *out /* kTableWords */) {
+    for (int si = 0; si < 2; ++si) {
+        const int s = si ? 1 : -1;
+        for (int n = -12; n <= 12; ++n)
+            out[si * 25 + n + 12] = threshold_of(s * (20 * n + h), T);
+    }
+    out[50] = out[51] = 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct isf_lattice {
+    isf_desc d;
+    LatDev L;
+    AuxLayout aux;
+    uint8_t *aux_dev;
+    hipStream_t stream;
+    int device;
+    Tiling tiling;
+    bool use_graph;
+    int64_t n_occ, n_bonds;
+    // loaded schedule, mirrored on the host
+    uint32_t sched_steps;
+    uint64_t sched_total;      // sweeps in the loaded schedule
+    uint64_t sched_enqueued;   // sweeps enqueued so far
+    // cached graph of graph_sweeps sweeps
+    hipGraphExec_t graph;
+    uint32_t graph_sweeps;
+    Tiling graph_tiling;
+};
+
+struct isf_batch {
+    uint32_t max_lats;
+    uint8_t *ws_dev;
+    uint64_t ws_bytes;
+    hipStream_t stream;
+    BatchEntry *staging;   // pinned host
+    hipEvent_t staged;     // recorded after the last staging copy
+    bool persistent_used;  // a persistent launch ran since the last check
+};
+
+namespace {
+
+int32_t set_device_of(const isf_lattice *lat) {
+    HIP_TRY(hipSetDevice(lat->device));
+    return ISF_OK;
+}
+
+int32_t launch_phase(const isf_lattice *lat, uint32_t sigma) {
+    hipError_t e = lat->d.format == ISF_FORMAT_INT8 ? launch_phase_i8(lat->L, lat->tiling, sigma, lat->stream)
+                                                    : launch_phase_bp(lat->L, lat->tiling, sigma, lat->stream);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "phase launch failed: %s", hipGetErrorString(e));
+    return ISF_OK;
+}
+
+int32_t enqueue_sweeps_plain(const isf_lattice *lat, uint64_t n) {
+    for (uint64_t i = 0; i < n; ++i)
+        for (uint32_t s = 0; s < 4; ++s) {
+            int32_t rc = launch_phase(lat, s);
+            if (rc)
+                return rc;
+        }
+    return ISF_OK;
+}
+
+constexpr uint32_t kGraphSweeps = 64;
+
+void drop_graph(isf_lattice *lat) {
+    if (lat->graph) {
+        (void)hipGraphExecDestroy(lat->graph);
+        lat->graph = nullptr;
+    }
+}
+
+int32_t build_graph(isf_lattice *lat) {
+    drop_graph(lat);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(lat->stream, hipStreamCaptureModeThreadLocal));
+    int32_t rc = enqueue_sweeps_plain(lat, kGraphSweeps);
+    hipError_t e = hipStreamEndCapture(lat->stream, &g);
+    if (rc) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&lat->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        lat->graph = nullptr;
+        return fail(ISF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    lat->graph_sweeps = kGraphSweeps;
+    lat->graph_tiling = lat->tiling;
+    return ISF_OK;
+}
+
+int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
+    if (lat->use_graph && lat->stream && n >= kGraphSweeps) {
+        if (!lat->graph || lat->graph_tiling.tx != lat->tiling.tx || lat->graph_tiling.ty != lat->tiling.ty ||
+            lat->graph_tiling.ry != lat->tiling.ry) {
+            int32_t rc = build_graph(lat);
+            if (rc)
+                return rc;
+        }
+        while (n >= lat->graph_sweeps) {
+            HIP_TRY(hipGraphLaunch(lat->graph, lat->stream));
+            n -= lat->graph_sweeps;
+        }
+    }
+    return enqueue_sweeps_plain(lat, n);
+}
+
+// Compact start layout: vacancies 1, occupied sites 0 (INT8) or occupancy bits (BITPACK).
+void build_layout(const isf_desc &d, const uint8_t *h, std::vector<uint8_t> &buf) {
+    const uint32_t X = d.X, Y = d.Y, Z = d.Z, W = X / 2;
+    buf.assign(spin_bytes_of(&d), 0);
+    if (d.format == ISF_FORMAT_INT8) {
+        std::fill(buf.begin(), buf.end(), (uint8_t)1);
+        for (uint32_t z = 0; z < Z; ++z)
+            for (uint32_t y = 0; y < Y; ++y) {
+                uint8_t *row = &buf[((size_t)(z + 1) * Y + y) * W];
+                const uint32_t p = (y + z) & 1u;
+                for (uint32_t j = 0; j < W; ++j)
+                    if (z < h[(size_t)y * X + 2 * j + p])
+                        row[j] = 0;
+            }
+    } else {
+        const uint32_t nw = W / 32;
+        uint32_t *w = reinterpret_cast<uint32_t *>(buf.data());
+        for (uint32_t z = 0; z < Z; ++z)
+            for (uint32_t y = 0; y < Y; ++y) {
+                uint32_t *occ = w + (((size_t)(z + 1) * Y + y) * 2 + 1) * nw;
+                const uint32_t p = (y + z) & 1u;
+                for (uint32_t j = 0; j < W; ++j)
+                    if (z < h[(size_t)y * X + 2 * j + p])
+                        occ[j >> 5] |= 1u << (j & 31);
+            }
+    }
+}
+
+int32_t recount(isf_lattice *lat, int64_t out[4]) {
+    // scratch: the record area's first 32 bytes are free outside a schedule run;
+    // use a dedicated spot after the slots instead to keep records intact.
+    int64_t *dev = reinterpret_cast<int64_t *>(lat->aux_dev + lat->aux.off_slots) + 3;  // slot 0 pad words
+    HIP_TRY(hipMemsetAsync(dev, 0, 4 * sizeof(int64_t), lat->stream));
+    hipError_t e = lat->d.format == ISF_FORMAT_INT8 ? launch_recount_i8(lat->L, dev, lat->stream)
+                                                    : launch_recount_bp(lat->L, dev, lat->stream);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "recount launch: %s", hipGetErrorString(e));
+    HIP_TRY(hipMemcpyAsync(out, dev, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return ISF_OK;
+}
+
+// Write M, E, t and counts into the device state.
+int32_t put_state(isf_lattice *lat, int64_t M, int64_t E, uint64_t t) {
+    struct {
+        int64_t M, E;
+        uint64_t t;
+    } head = {M, E, t};
+    HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, M), &head, sizeof head, hipMemcpyHostToDevice,
+                           lat->stream));
+    int64_t counts[2] = {lat->n_occ, lat->n_bonds};
+    HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, n_occ), counts, sizeof counts, hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return ISF_OK;
+}
+
+int32_t check_lat(const isf_lattice *lat) {
+    if (!lat)
+        return fail(ISF_EINVAL, "null lattice handle");
+    return ISF_OK;
+}
+
+int32_t validate_steps(const isf_step *steps, uint32_t n) {
+    if (n && !steps)
+        return fail(ISF_EINVAL, "null steps");
+    for (uint32_t i = 0; i < n; ++i) {
+        int32_t rc = validate_T(steps[i].T);
+        if (rc)
+            return rc;
+        rc = validate_h(steps[i].h_num);
+        if (rc)
+            return rc;
+        if (steps[i].n_sweeps < 1)
+            return fail(ISF_EINVAL, "step %u: n_sweeps must be >= 1", i);
+        if (steps[i].n_discard > steps[i].n_sweeps)
+            return fail(ISF_EINVAL, "step %u: n_discard > n_sweeps", i);
+        if (steps[i].reserved)
+            return fail(ISF_EINVAL, "step %u: reserved must be 0", i);
+    }
+    return ISF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t isf_abi_version(void) { return ISF_ABI_VERSION; }
+
+const char *isf_last_error(void) { return g_err.c_str(); }
+
+int32_t isf_lattice_bytes(const isf_desc *d, uint64_t *spin_bytes, uint64_t *aux_bytes) {
+    int32_t rc = validate_desc(d);
+    if (rc)
+        return rc;
+    if (!spin_bytes || !aux_bytes)
+        return fail(ISF_EINVAL, "null output pointer");
+    *spin_bytes = spin_bytes_of(d);
+    *aux_bytes = aux_layout(ISF_MAX_STEPS).total;
+    return ISF_OK;
+}
+
+int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]) {
+    int32_t rc = validate_T(T);
+    if (rc)
+        return rc;
+    if ((rc = validate_h(h_num)))
+        return rc;
+    if (!out)
+        return fail(ISF_EINVAL, "null output");
+    uint32_t tab[kTableWords];
+    table_of(T, h_num, tab);
+    std::memcpy(out, tab, 50 * sizeof(uint32_t));
+    return ISF_OK;
+}
+
+int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t init, void *spin_dev,
+                           uint64_t spin_bytes, void *aux_dev, uint64_t aux_bytes, void *stream, isf_lattice **out) {
+    int32_t rc = validate_desc(d);
+    if (rc)
+        return rc;
+    if (!h_host || !spin_dev || !aux_dev || !out)
+        return fail(ISF_EINVAL, "null pointer argument");
+    if (init != ISF_INIT_UP && init != ISF_INIT_DOWN && init != ISF_INIT_RANDOM)
+        return fail(ISF_EINVAL, "unknown init mode %d", init);
+    const uint64_t need_spin = spin_bytes_of(d);
+    const AuxLayout al = aux_layout(ISF_MAX_STEPS);
+    if (spin_bytes < need_spin || aux_bytes < al.total)
+        return fail(ISF_ENOSPC, "buffers too small: need %llu + %llu bytes", (unsigned long long)need_spin,
+                    (unsigned long long)al.total);
+    if (((uintptr_t)spin_dev & 255) || ((uintptr_t)aux_dev & 255))
+        return fail(ISF_EINVAL, "device buffers must be 256-byte aligned");
+    for (uint64_t i = 0, n = (uint64_t)d->X * d->Y; i < n; ++i)
+        if (h_host[i] > d->Z)
+            return fail(ISF_EINVAL, "height map value %u at %llu exceeds Z=%u", h_host[i], (unsigned long long)i, d->Z);
+
+    isf_lattice *lat = new (std::nothrow) isf_lattice();
+    if (!lat)
+        return fail(ISF_EINVAL, "out of host memory");
+    lat->d = *d;
+    lat->aux = al;
+    lat->aux_dev = static_cast<uint8_t *>(aux_dev);
+    lat->stream = static_cast<hipStream_t>(stream);
+    lat->tiling = Tiling{64, 4, 2};
+    lat->use_graph = true;
+    if (hipGetDevice(&lat->device) != hipSuccess) {
+        delete lat;
+        return fail(ISF_EHIP, "hipGetDevice failed");
+    }
+    LatDev &L = lat->L;
+    L.spins = static_cast<uint8_t *>(spin_dev);
+    L.st = reinterpret_cast<DevState *>(lat->aux_dev + al.off_state);
+    L.slots = reinterpret_cast<Slot *>(lat->aux_dev + al.off_slots);
+    L.steps = reinterpret_cast<StepDesc *>(lat->aux_dev + al.off_steps);
+    L.tables = reinterpret_cast<uint32_t *>(lat->aux_dev + al.off_tables);
+    L.records = reinterpret_cast<isf_record *>(lat->aux_dev + al.off_records);
+    L.X = d->X;
+    L.Y = d->Y;
+    L.Z = d->Z;
+    L.W = d->X / 2;
+    L.nd = d->format == ISF_FORMAT_INT8 ? L.W / 4 : L.W / 32;
+    L.key0 = (uint32_t)d->seed;
+    L.key1 = (uint32_t)(d->seed >> 32);
+    L.replica = d->replica;
+    L.format = d->format;
+
+    auto bail = [&](int32_t code) {
+        delete lat;
+        return code;
+    };
+    std::vector<uint8_t> buf;
+    build_layout(*d, h_host, buf);
+    if (hipMemsetAsync(aux_dev, 0, al.total, lat->stream) != hipSuccess ||
+        hipMemcpyAsync(spin_dev, buf.data(), buf.size(), hipMemcpyHostToDevice, lat->stream) != hipSuccess)
+        return bail(fail(ISF_EHIP, "initial upload failed"));
+    hipError_t e = d->format == ISF_FORMAT_INT8 ? launch_init_i8(L, init, lat->stream)
+                                                : launch_init_bp(L, init, lat->stream);
+    if (e != hipSuccess)
+        return bail(fail(ISF_EHIP, "init launch: %s", hipGetErrorString(e)));
+    int64_t cnt[4];
+    if ((rc = recount(lat, cnt)))
+        return bail(rc);
+    lat->n_occ = cnt[2];
+    lat->n_bonds = cnt[3] / 2;
+    if ((rc = put_state(lat, cnt[0], -cnt[1] / 2, 0)))
+        return bail(rc);
+    *out = lat;
+    return ISF_OK;
+}
+
+int32_t isf_lattice_destroy(isf_lattice *lat) {
+    if (!lat)
+        return fail(ISF_EINVAL, "null lattice handle");
+    drop_graph(lat);
+    delete lat;
+    return ISF_OK;
+}
+
+int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!t)
+        return fail(ISF_EINVAL, "null tuning");
+    Tiling tl{t->tile_x, t->tile_y, t->rows_per_thread};
+    const bool ok = lat->d.format == ISF_FORMAT_INT8 ? tiling_supported(tl) : tiling_supported_bp(tl);
+    if (!ok)
+        return fail(ISF_EINVAL, "unsupported tiling %ux%ux%u", tl.tx, tl.ty, tl.ry);
+    lat->tiling = tl;
+    lat->use_graph = t->use_graph != 0;
+    return ISF_OK;
+}
+
+int32_t isf_get_tuning(const isf_lattice *lat, isf_tuning *t) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!t)
+        return fail(ISF_EINVAL, "null tuning");
+    t->tile_x = lat->tiling.tx;
+    t->tile_y = lat->tiling.ty;
+    t->rows_per_thread = lat->tiling.ry;
+    t->use_graph = lat->use_graph;
+    return ISF_OK;
+}
+
+int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (n > ISF_MAX_STEPS)
+        return fail(ISF_EINVAL, "schedule of %u steps exceeds %u", n, (unsigned)ISF_MAX_STEPS);
+    if ((rc = validate_steps(steps, n)))
+        return rc;
+    if ((rc = set_device_of(lat)))
+        return rc;
+    std::vector<StepDesc> sd(n ? n : 1);
+    std::vector<uint32_t> tabs((size_t)(n ? n : 1) * kTableWords, 0);
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        sd[i] = StepDesc{steps[i].n_sweeps, steps[i].n_discard};
+        table_of(steps[i].T, steps[i].h_num, &tabs[(size_t)i * kTableWords]);
+        total += steps[i].n_sweeps;
+    }
+    struct {
+        uint32_t step, sweep_in_step;
+        int64_t sum_M, sum_absM, sum_E, accepted;
+        uint32_t done_ctr, n_steps;
+    } mid = {0, 0, 0, 0, 0, 0, 0, n};
+    static_assert(offsetof(DevState, n_steps) + 4 - offsetof(DevState, step) == sizeof(mid), "state layout");
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(lat->L.steps, sd.data(), sizeof(StepDesc) * n, hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(hipMemcpyAsync(lat->L.tables, tabs.data(), sizeof(uint32_t) * kTableWords * n,
+                               hipMemcpyHostToDevice, lat->stream));
+        HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, cur_table), tabs.data(),
+                               sizeof(uint32_t) * kTableWords, hipMemcpyHostToDevice, lat->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, step), &mid, sizeof mid, hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->sched_steps = n;
+    lat->sched_total = total;
+    lat->sched_enqueued = 0;
+    return ISF_OK;
+}
+
+int32_t isf_schedule_remaining(const isf_lattice *lat, uint64_t *sweeps) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!sweeps)
+        return fail(ISF_EINVAL, "null output");
+    *sweeps = lat->sched_total - lat->sched_enqueued;
+    return ISF_OK;
+}
+
+int32_t isf_advance(isf_lattice *lat, uint32_t max_sweeps, uint64_t *enqueued) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if ((rc = set_device_of(lat)))
+        return rc;
+    const uint64_t n = std::min<uint64_t>(max_sweeps, lat->sched_total - lat->sched_enqueued);
+    if ((rc = enqueue_sweeps(lat, n)))
+        return rc;
+    lat->sched_enqueued += n;
+    if (enqueued)
+        *enqueued = n;
+    return ISF_OK;
+}
+
+int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (n > lat->sched_steps)
+        return fail(ISF_EINVAL, "asked for %u records of a %u-step schedule", n, lat->sched_steps);
+    if (n && !out)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    if (n)
+        HIP_TRY(hipMemcpyAsync(out, lat->L.records, sizeof(isf_record) * n, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return ISF_OK;
+}
+
+int32_t isf_run_schedule(isf_lattice *lat, const isf_step *steps, uint32_t n_steps, isf_record *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (n_steps && !out)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = validate_steps(steps, n_steps)))
+        return rc;
+    for (uint32_t base = 0; base < n_steps; base += ISF_MAX_STEPS) {
+        const uint32_t n = std::min<uint32_t>(ISF_MAX_STEPS, n_steps - base);
+        if ((rc = isf_schedule_load(lat, steps + base, n)))
+            return rc;
+        uint64_t done = 0;
+        if ((rc = isf_advance(lat, 0xFFFFFFFFu, &done)))
+            return rc;
+        if ((rc = isf_schedule_records(lat, out + base, n)))
+            return rc;
+    }
+    return ISF_OK;
+}
+
+int32_t isf_read_observables(isf_lattice *lat, isf_obs *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    struct {
+        int64_t M, E;
+        uint64_t t;
+    } head;
+    HIP_TRY(hipMemcpyAsync(&head, lat->aux_dev, sizeof head, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    out->M = head.M;
+    out->E = head.E;
+    out->n_occ = lat->n_occ;
+    out->n_bonds = lat->n_bonds;
+    out->sweeps = head.t;
+    return ISF_OK;
+}
+
+int32_t isf_run_sweeps(isf_lattice *lat, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_discard,
+                       isf_record *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = validate_T(T)) || (rc = validate_h(h_num)))
+        return rc;
+    if (n_discard > n_sweeps)
+        return fail(ISF_EINVAL, "n_discard > n_sweeps");
+    if (n_sweeps == 0) {
+        isf_obs o;
+        if ((rc = isf_read_observables(lat, &o)))
+            return rc;
+        *out = isf_record{o.M, o.E, 0, 0, 0, 0};
+        return ISF_OK;
+    }
+    isf_step st{T, h_num, n_sweeps, n_discard, 0};
+    return isf_run_schedule(lat, &st, 1, out);
+}
+
+int32_t isf_ramp_field(isf_lattice *lat, double T, const int32_t *h_num, uint32_t n_steps, uint32_t sweeps_per_step,
+                       isf_record *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (n_steps && (!h_num || !out))
+        return fail(ISF_EINVAL, "null pointer argument");
+    if (sweeps_per_step < 1)
+        return fail(ISF_EINVAL, "sweeps_per_step must be >= 1");
+    std::vector<isf_step> st(n_steps);
+    for (uint32_t i = 0; i < n_steps; ++i)
+        st[i] = isf_step{T, h_num[i], sweeps_per_step, 0, 0};
+    return isf_run_schedule(lat, st.data(), n_steps, out);
+}
+
+int32_t isf_temperature_scan(isf_lattice *lat, const double *T, uint32_t n_T, int32_t h_num, uint32_t sweeps_per_T,
+                             uint32_t discard_per_T, isf_record *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (n_T && (!T || !out))
+        return fail(ISF_EINVAL, "null pointer argument");
+    std::vector<isf_step> st(n_T);
+    for (uint32_t i = 0; i < n_T; ++i)
+        st[i] = isf_step{T[i], h_num, sweeps_per_T, discard_per_T, 0};
+    return isf_run_schedule(lat, st.data(), n_T, out);
+}
+
+int32_t isf_read_spins(isf_lattice *lat, int8_t *cube) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!cube)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    const isf_desc &d = lat->d;
+    std::vector<uint8_t> buf(spin_bytes_of(&d));
+    HIP_TRY(hipMemcpyAsync(buf.data(), lat->L.spins, buf.size(), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    const uint32_t X = d.X, Y = d.Y, Z = d.Z, W = X / 2;
+    std::memset(cube, 0, (size_t)X * Y * Z);
+    for (uint32_t z = 0; z < Z; ++z)
+        for (uint32_t y = 0; y < Y; ++y) {
+            const uint32_t p = (y + z) & 1u;
+            int8_t *out = cube + ((size_t)z * Y + y) * X;
+            if (d.format == ISF_FORMAT_INT8) {
+                const uint8_t *row = &buf[((size_t)(z + 1) * Y + y) * W];
+                for (uint32_t j = 0; j < W; ++j)
+                    out[2 * j + p] = row[j] == 1 ? 0 : (int8_t)((int)row[j] - 1);
+            } else {
+                const uint32_t nw = W / 32;
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(buf.data()) + ((size_t)(z + 1) * Y + y) * 2 * nw;
+                for (uint32_t j = 0; j < W; ++j) {
+                    const uint32_t up = (w[j >> 5] >> (j & 31)) & 1u, oc = (w[nw + (j >> 5)] >> (j & 31)) & 1u;
+                    out[2 * j + p] = oc ? (up ? 1 : -1) : 0;
+                }
+            }
+        }
+    return ISF_OK;
+}
+
+int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube, uint64_t sweeps) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!cube)
+        return fail(ISF_EINVAL, "null input");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    const isf_desc &d = lat->d;
+    std::vector<uint8_t> buf(spin_bytes_of(&d));
+    HIP_TRY(hipMemcpyAsync(buf.data(), lat->L.spins, buf.size(), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    const uint32_t X = d.X, Y = d.Y, Z = d.Z, W = X / 2;
+    for (uint32_t z = 0; z < Z; ++z)
+        for (uint32_t y = 0; y < Y; ++y) {
+            const uint32_t p = (y + z) & 1u;
+            const int8_t *in = cube + ((size_t)z * Y + y) * X;
+            if (d.format == ISF_FORMAT_INT8) {
+                uint8_t *row = &buf[((size_t)(z + 1) * Y + y) * W];
+                for (uint32_t j = 0; j < W; ++j) {
+                    if (row[j] == 1)
+                        continue;  // vacancy
+                    const int8_t s = in[2 * j + p];
+                    if (s != 1 && s != -1)
+                        return fail(ISF_EINVAL, "occupied site (%u,%u,%u) holds %d, not +-1", 2 * j + p, y, z, s);
+                    row[j] = (uint8_t)(s + 1);
+                }
+            } else {
+                const uint32_t nw = W / 32;
+                uint32_t *w = reinterpret_cast<uint32_t *>(buf.data()) + ((size_t)(z + 1) * Y + y) * 2 * nw;
+                for (uint32_t j = 0; j < W; ++j) {
+                    if (!((w[nw + (j >> 5)] >> (j & 31)) & 1u))
+                        continue;
+                    const int8_t s = in[2 * j + p];
+                    if (s != 1 && s != -1)
+                        return fail(ISF_EINVAL, "occupied site (%u,%u,%u) holds %d, not +-1", 2 * j + p, y, z, s);
+                    if (s > 0)
+                        w[j >> 5] |= 1u << (j & 31);
+                    else
+                        w[j >> 5] &= ~(1u << (j & 31));
+                }
+            }
+        }
+    HIP_TRY(hipMemcpyAsync(lat->L.spins, buf.data(), buf.size(), hipMemcpyHostToDevice, lat->stream));
+    int64_t cnt[4];
+    if ((rc = recount(lat, cnt)))
+        return rc;
+    return put_state(lat, cnt[0], -cnt[1] / 2, sweeps);
+}
+
+int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uint32_t *swept) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!ms || !swept)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    const uint32_t n = (uint32_t)std::min<uint64_t>(n_sweeps, lat->sched_total - lat->sched_enqueued);
+    std::vector<hipEvent_t> ev(8 * (size_t)n);
+    for (auto &e : ev)
+        HIP_TRY(hipEventCreate(&e));
+    int32_t status = ISF_OK;
+    for (uint32_t i = 0; i < n && status == ISF_OK; ++i)
+        for (uint32_t s = 0; s < 4 && status == ISF_OK; ++s) {
+            (void)hipEventRecord(ev[8 * i + 2 * s], lat->stream);
+            status = launch_phase(lat, s);
+            (void)hipEventRecord(ev[8 * i + 2 * s + 1], lat->stream);
+        }
+    double sum[4] = {0, 0, 0, 0};
+    if (status == ISF_OK) {
+        lat->sched_enqueued += n;
+        if (hipStreamSynchronize(lat->stream) != hipSuccess)
+            status = fail(ISF_EHIP, "stream synchronisation failed");
+        for (uint32_t i = 0; i < n && status == ISF_OK; ++i)
+            for (uint32_t s = 0; s < 4; ++s) {
+                float m = 0.f;
+                if (hipEventElapsedTime(&m, ev[8 * i + 2 * s], ev[8 * i + 2 * s + 1]) != hipSuccess) {
+                    status = fail(ISF_EHIP, "hipEventElapsedTime failed");
+                    break;
+                }
+                sum[s] += m;
+            }
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    if (status)
+        return status;
+    for (int s = 0; s < 4; ++s)
+        ms[s] = n ? sum[s] / n : 0.0;
+    *swept = n;
+    return ISF_OK;
+}
+
+int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!M || !E)
+        return fail(ISF_EINVAL, "null output");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    int64_t cnt[4];
+    if ((rc = recount(lat, cnt)))
+        return rc;
+    *M = cnt[0];
+    *E = -cnt[1] / 2;
+    return ISF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+
+int32_t isf_batch_workspace_bytes(uint32_t max_lats, uint64_t *bytes) {
+    if (!bytes || max_lats == 0)
+        return fail(ISF_EINVAL, "bad arguments");
+    *bytes = ((uint64_t)sizeof(BatchEntry) * max_lats + 256 + 255) / 256 * 256;
+    return ISF_OK;
+}
+
+int32_t isf_batch_create(uint32_t max_lats, void *ws, uint64_t ws_bytes, void *stream, isf_batch **out) {
+    uint64_t need = 0;
+    int32_t rc = isf_batch_workspace_bytes(max_lats, &need);
+    if (rc)
+        return rc;
+    if (!ws || !out)
+        return fail(ISF_EINVAL, "null pointer argument");
+    if (ws_bytes < need)
+        return fail(ISF_ENOSPC, "workspace of %llu bytes < %llu", (unsigned long long)ws_bytes,
+                    (unsigned long long)need);
+    if ((uintptr_t)ws & 255)
+        return fail(ISF_EINVAL, "workspace must be 256-byte aligned");
+    isf_batch *b = new (std::nothrow) isf_batch();
+    if (!b)
+        return fail(ISF_EINVAL, "out of host memory");
+    b->max_lats = max_lats;
+    b->ws_dev = static_cast<uint8_t *>(ws);
+    b->ws_bytes = ws_bytes;
+    b->stream = static_cast<hipStream_t>(stream);
+    if (hipHostMalloc((void **)&b->staging, sizeof(BatchEntry) * max_lats, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return fail(ISF_EHIP, "hipHostMalloc of the staging area failed");
+    }
+    if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(b->staging);
+        delete b;
+        return fail(ISF_EHIP, "hipEventCreate failed");
+    }
+    *out = b;
+    return ISF_OK;
+}
+
+int32_t isf_batch_destroy(isf_batch *b) {
+    if (!b)
+        return fail(ISF_EINVAL, "null batch");
+    (void)hipEventSynchronize(b->staged);
+    (void)hipEventDestroy(b->staged);
+    (void)hipHostFree(b->staging);
+    delete b;
+    return ISF_OK;
+}
+
+int32_t isf_batch_sync(isf_batch *b) {
+    if (!b)
+        return fail(ISF_EINVAL, "null batch");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->persistent_used) {
+        uint32_t flag = 0;
+        HIP_TRY(hipMemcpy(&flag, b->ws_dev + sizeof(BatchEntry) * b->max_lats + sizeof(uint32_t), sizeof flag,
+                          hipMemcpyDeviceToHost));
+        if (flag)
+            return fail(ISF_EHIP, "persistent kernel: grid barrier timed out; results are invalid");
+    }
+    return ISF_OK;
+}
+
+int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps, int32_t mode,
+                          uint64_t *enqueued_out) {
+    if (!b || (n && !lats))
+        return fail(ISF_EINVAL, "null pointer argument");
+    if (n > b->max_lats)
+        return fail(ISF_EINVAL, "%u lattices exceed the batch capacity %u", n, b->max_lats);
+    if (mode != ISF_BATCH_PHASE_LAUNCH && mode != ISF_BATCH_PERSISTENT)
+        return fail(ISF_EINVAL, "unknown batch mode %d", mode);
+    if (n == 0) {
+        if (enqueued_out)
+            *enqueued_out = 0;
+        return ISF_OK;
+    }
+    const uint32_t format = lats[0]->d.format;
+    const Tiling tl = lats[0]->tiling;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!lats[i])
+            return fail(ISF_EINVAL, "null lattice %u", i);
+        if (lats[i]->d.format != format)
+            return fail(ISF_ESTATE, "lattices of a batch must share one format");
+    }
+    // the staging area may still be read by the previous copy
+    HIP_TRY(hipEventSynchronize(b->staged));
+    uint64_t sweeps = 0;
+    uint32_t m = 0, blocks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        const uint64_t rem = lat->sched_total - lat->sched_enqueued;
+        if (rem == 0)
+            continue;
+        BatchEntry &e = b->staging[m++];
+        e.lat = lat->L;
+        e.block_begin = blocks;
+        if (format == ISF_FORMAT_INT8)
+            batch_grid_i8(lat->L, tl, e.nbx, e.nby, e.nbz);
+        else
+            batch_grid_bp(lat->L, tl, e.nbx, e.nby, e.nbz);
+        blocks += e.nbx * e.nby * e.nbz;
+        sweeps = std::max<uint64_t>(sweeps, std::min<uint64_t>(rem, max_sweeps));
+    }
+    if (m == 0 || sweeps == 0) {
+        if (enqueued_out)
+            *enqueued_out = 0;
+        return ISF_OK;
+    }
+    BatchEntry *ents = reinterpret_cast<BatchEntry *>(b->ws_dev);
+    uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + sizeof(BatchEntry) * b->max_lats);
+    HIP_TRY(hipMemcpyAsync(ents, b->staging, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipEventRecord(b->staged, b->stream));
+    if (mode == ISF_BATCH_PHASE_LAUNCH) {
+        for (uint64_t sw = 0; sw < sweeps; ++sw)
+            for (uint32_t s = 0; s < 4; ++s) {
+                hipError_t e = format == ISF_FORMAT_INT8
+                                   ? launch_phase_i8_batch(ents, m, blocks, tl, s, b->stream)
+                                   : launch_phase_bp_batch(ents, m, blocks, tl, s, b->stream);
+                if (e != hipSuccess)
+                    return fail(ISF_EHIP, "batched phase launch: %s", hipGetErrorString(e));
+            }
+    } else {
+        uint32_t grid = 0;
+        hipError_t e = launch_persistent(ents, m, blocks, format, tl, (uint32_t)sweeps, barrier, b->stream, &grid);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "persistent launch: %s", hipGetErrorString(e));
+        b->persistent_used = true;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        lat->sched_enqueued += std::min<uint64_t>(lat->sched_total - lat->sched_enqueued, sweeps);
+    }
+    if (enqueued_out)
+        *enqueued_out = sweeps;
+    return ISF_OK;
+}
+
+int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n, const isf_step *const *steps,
+                      const uint32_t *n_steps, isf_record *const *out, int32_t mode) {
+    if (!b || (n && (!lats || !steps || !n_steps || !out)))
+        return fail(ISF_EINVAL, "null pointer argument");
+    int32_t rc;
+    for (uint32_t i = 0; i < n; ++i)
+        if ((rc = isf_schedule_load(lats[i], steps[i], n_steps[i])))
+            return rc;
+    uint64_t got = 0;
+    if ((rc = isf_batch_advance(b, lats, n, 0xFFFFFFFFu, mode, &got)))
+        return rc;
+    if ((rc = isf_batch_sync(b)))
+        return rc;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (n_steps[i] && !out[i])
+            return fail(ISF_EINVAL, "null record buffer %u", i);
+        if (n_steps[i])
+            HIP_TRY(hipMemcpy(out[i], lats[i]->L.records, sizeof(isf_record) * n_steps[i], hipMemcpyDeviceToHost));
+    }
+    return ISF_OK;
+}
+
+}  // extern "C"

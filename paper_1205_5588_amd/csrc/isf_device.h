@@ -1,0 +1,203 @@
+// Device helpers shared by the sweep kernels (INT8, BITPACK, persistent).
+//
+// Per-sweep bookkeeping: blocks add their flips' changes of M (-2 s_old) and
+// E_bond (+2 s_old n) to 64 spread slots with relaxed agent-scope atomics;
+// the last block of the last sublattice of a sweep (found with an atomic
+// counter) folds the slots into M and E, advances the sweep counter, adds the
+// sweep to the step's sums if it is kept, writes the step record when the
+// step ends and stages the next step's threshold table.  All device-state
+// accesses that other blocks of the same launch may race with use agent-scope
+// atomics, so the same code serves one launch per sublattice and the
+// persistent kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "isf_internal.h"
+
+namespace isf {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).  The key and three of
+// the four counter words are uniform across a wave, so the compiler keeps the
+// key schedule and the first round's uniform product in scalar registers.
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                       uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T ald(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void ast(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T aadd(T *p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stage a film's current table and sweep counter into LDS.  Block-wide;
+// ends with a barrier.  Returns false if the film's schedule is finished.
+__device__ __forceinline__ bool stage_film(const LatDev &L, uint32_t *tab, uint32_t *t_sh, uint32_t *run_sh) {
+    if (threadIdx.x < kTableWords)
+        tab[threadIdx.x] = ald(&L.st->cur_table[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        *t_sh = (uint32_t)ald(&L.st->t);
+        *run_sh = ald(&L.st->step) < ald(&L.st->n_steps);
+    }
+    __syncthreads();
+    return *run_sh != 0;
+}
+
+// Sweep end, run by the 64 lanes of one wave.
+__device__ inline void sweep_end(const LatDev &L) {
+    const uint32_t lane = threadIdx.x & 63;
+    __threadfence();
+    int64_t dM = 0, dE = 0, acc = 0;
+    for (uint32_t s = lane; s < kSlots; s += 64) {
+        dM += ald(&L.slots[s].dM);
+        dE += ald(&L.slots[s].dE);
+        acc += ald(&L.slots[s].acc);
+        ast(&L.slots[s].dM, (int64_t)0);
+        ast(&L.slots[s].dE, (int64_t)0);
+        ast(&L.slots[s].acc, (int64_t)0);
+    }
+    dM = wave_sum(dM);
+    dE = wave_sum(dE);
+    acc = wave_sum(acc);
+    DevState *st = L.st;
+    uint32_t next_step = 0xFFFFFFFFu;
+    if (lane == 0) {
+        const int64_t M = ald(&st->M) + dM;
+        const int64_t E = ald(&st->E) + dE;
+        ast(&st->M, M);
+        ast(&st->E, E);
+        ast(&st->t, ald(&st->t) + 1);
+        uint32_t step = ald(&st->step);
+        uint32_t sis = ald(&st->sweep_in_step);
+        if (step < ald(&st->n_steps)) {
+            const uint32_t n_sweeps = ald(&L.steps[step].n_sweeps);
+            const uint32_t n_discard = ald(&L.steps[step].n_discard);
+            int64_t sM = ald(&st->sum_M), sA = ald(&st->sum_absM), sE = ald(&st->sum_E), sC = ald(&st->accepted);
+            if (sis >= n_discard) {
+                sM += M;
+                sA += M < 0 ? -M : M;
+                sE += E;
+                sC += acc;
+            }
+            ++sis;
+            if (sis >= n_sweeps) {
+                isf_record *rec = &L.records[step];
+                ast(&rec->M, M);
+                ast(&rec->E, E);
+                ast(&rec->sum_M, sM);
+                ast(&rec->sum_absM, sA);
+                ast(&rec->sum_E, sE);
+                ast(&rec->accepted, sC);
+                sM = sA = sE = sC = 0;
+                ++step;
+                sis = 0;
+                if (step < ald(&st->n_steps))
+                    next_step = step;
+            }
+            ast(&st->sum_M, sM);
+            ast(&st->sum_absM, sA);
+            ast(&st->sum_E, sE);
+            ast(&st->accepted, sC);
+            ast(&st->step, step);
+            ast(&st->sweep_in_step, sis);
+        }
+        ast(&st->done_ctr, 0u);
+    }
+    next_step = __shfl(next_step, 0, 64);
+    if (next_step != 0xFFFFFFFFu && lane < kTableWords)
+        ast(&st->cur_table[lane], ald(&L.tables[(size_t)next_step * kTableWords + lane]));
+    __threadfence();
+}
+
+// Block reduction of the per-thread partial sums, slot atomics, and on the
+// last sublattice the sweep end of the last block of the film.
+template <int NT>
+__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat,
+                                             uint32_t blocks_in_lat, bool last_phase) {
+    __shared__ int red[3][NT / 64];
+    __shared__ uint32_t is_last;
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    dM = wave_sum(dM);
+    dE = wave_sum(dE);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        red[0][wid] = dM;
+        red[1][wid] = dE;
+        red[2][wid] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sM = 0, sE = 0, sA = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            sM += red[0][w];
+            sE += red[1][w];
+            sA += red[2][w];
+        }
+        Slot *slot = &L.slots[block_in_lat % kSlots];
+        if (sA) {
+            aadd(&slot->dM, sM);
+            aadd(&slot->dE, sE);
+            aadd(&slot->acc, sA);
+        }
+        uint32_t last = 0;
+        if (last_phase) {
+            __threadfence();
+            const uint32_t prev = aadd(&L.st->done_ctr, 1u);
+            last = (prev + 1 == blocks_in_lat);
+        }
+        is_last = last;
+    }
+    __syncthreads();
+    if (is_last && threadIdx.x < 64)
+        sweep_end(L);
+    __syncthreads();
+}
+
+// Linear block index -> film entry of a batched launch table (binary search).
+__device__ __forceinline__ uint32_t find_entry(const BatchEntry *ents, uint32_t n, uint32_t b) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ents[mid].block_begin <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace isf

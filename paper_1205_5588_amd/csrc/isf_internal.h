@@ -1,0 +1,110 @@
+// Internal layout shared by the host side of the library and its HIP kernels.
+//
+// Storage of one film (INT8 format), in the caller's spin buffer:
+//   compact rows: site (x, y, z) with x+y+z even lives in row (y, z) at column
+//   j = x / 2, so a row holds W = X/2 bytes and X = 2j + ((y+z) & 1);
+//   planes z = -1 and z = Z are padding rows of vacancies, so the buffer is
+//   [Z+2][Y][W] bytes and the open z boundary needs no test in the kernels;
+//   a byte holds s + 1 for an occupied site (0: down, 2: up) and 1 for a
+//   vacancy, so the sum of the 12 neighbour bytes of a site is n + 12 in
+//   [0, 24] (a vacancy adds 1 = 0 + 1).  Four sites share one dword and
+//   twelve dwords add without carries between bytes.
+//
+// BITPACK format: per row two bit planes of W bits (W/32 words each): spin
+//   bit (1 = up) and occupancy bit; planes z = -1 and z = Z are zero words.
+//   Layout [Z+2][Y][2][W/32] uint32 (spin words then occupancy words).
+//
+// Neighbours of the site at row (y, z), column j (p = (y+z) & 1, delta = -1
+// if p == 0 else +1, columns mod W): rows (y+-1, z) and (y, z+-1) at columns
+// j and j+delta; rows (y+-1, z+-1) at column j.
+#pragma once
+
+#include <stdint.h>
+
+#include "isf.h"
+
+namespace isf {
+
+constexpr uint32_t kSlots = 64;          // spread of the per-sweep atomic accumulators
+constexpr uint32_t kTableWords = 52;     // 50 thresholds, padded
+constexpr uint32_t kDefaultMaxSteps = 1024;
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+
+// Per-film device state, at offset 0 of the aux buffer.
+struct alignas(256) DevState {
+    int64_t M;              // tracked magnetisation
+    int64_t E;              // tracked bond energy
+    uint64_t t;             // sweep counter (Philox counter word 1, mod 2^32)
+    uint32_t step;          // current step of the loaded schedule
+    uint32_t sweep_in_step; // sweeps done in the current step
+    int64_t sum_M;          // accumulators of the current step (kept sweeps)
+    int64_t sum_absM;
+    int64_t sum_E;
+    int64_t accepted;
+    uint32_t done_ctr;      // blocks finished in the current last-phase launch
+    uint32_t n_steps;       // length of the loaded schedule
+    int64_t n_occ;
+    int64_t n_bonds;
+    uint32_t cur_table[kTableWords];  // thresholds of the current step
+};
+
+// Per-sweep partial sums, one 128-byte line each so that atomics spread.
+struct alignas(128) Slot {
+    int64_t dM;
+    int64_t dE;
+    int64_t acc;
+    int64_t pad[13];
+};
+
+struct StepDesc {
+    uint32_t n_sweeps;
+    uint32_t n_discard;
+};
+
+// Everything a kernel needs to work on one film.
+struct LatDev {
+    uint8_t *spins;       // INT8: [Z+2][Y][W] bytes; BITPACK: [Z+2][Y][2][W/32] words
+    DevState *st;
+    Slot *slots;          // [kSlots]
+    StepDesc *steps;      // [max_steps]
+    uint32_t *tables;     // [max_steps][kTableWords]
+    isf_record *records;  // [max_steps]
+    uint32_t X, Y, Z;
+    uint32_t W;           // compact sites per row = X/2
+    uint32_t nd;          // INT8: dwords per row = W/4; BITPACK: words per row = W/32
+    uint32_t key0, key1;
+    uint32_t replica;
+    uint32_t format;
+    uint32_t pad;
+};
+
+// Aux buffer layout.
+struct AuxLayout {
+    uint64_t off_state, off_slots, off_steps, off_tables, off_records, total;
+};
+
+inline AuxLayout aux_layout(uint32_t max_steps) {
+    AuxLayout a;
+    auto up = [](uint64_t v, uint64_t al) { return (v + al - 1) / al * al; };
+    a.off_state = 0;
+    a.off_slots = up(sizeof(DevState), 256);
+    a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 256);
+    a.off_tables = up(a.off_steps + sizeof(StepDesc) * max_steps, 256);
+    a.off_records = up(a.off_tables + sizeof(uint32_t) * kTableWords * max_steps, 256);
+    a.total = up(a.off_records + sizeof(isf_record) * max_steps, 256);
+    return a;
+}
+
+// Launch shape of the phase kernels.
+struct Tiling {
+    uint32_t tx, ty, ry;  // threads along a row (dwords / words), threads across rows, rows per thread
+};
+
+// One film in a batched launch: its description and where its blocks start.
+struct BatchEntry {
+    LatDev lat;
+    uint32_t block_begin;  // first linear block of this film in the launch
+    uint32_t nbx, nby, nbz;  // block grid of this film for the launch's phase
+};
+
+}  // namespace isf

@@ -1,0 +1,200 @@
+// HIP kernels for gfx950: Metropolis sweeps of the FCC-film Ising model.
+//
+// One launch updates one sublattice sigma = (y & 1) + 2 (z & 1) of a film
+// (Section 5, steps 1-3 of the Metropolis algorithm, Eq. 8; Hamiltonian
+// Eq. 3).  Sites of one sublattice share no bond, so every thread updates its
+// sites independently; four launches make one sweep.  The work is a
+// memory-bound integer stencil: no matrix cores.
+//
+// Layouts and the device state are described in isf_internal.h.
+//
+// Thread mapping: a thread owns one dword (4 consecutive compact sites of one
+// row, which is exactly one Philox4x32-10 call) in each of `RY` active rows.
+// A block is TX dwords x (TY * RY) active rows of one active plane; wave64
+// lanes run along the row, so all loads and stores are coalesced dwords.
+//
+// Observables: each accepted flip changes M by -2 s_old and E_bond by
+// +2 s_old n.  Blocks reduce these in registers and LDS and add them with
+// relaxed agent-scope atomics to one of 64 slots (spread over 128-byte lines).
+// The last block of the last sublattice of a sweep (found with an atomic
+// counter) folds the slots into M and E, advances the sweep counter, updates
+// the step's sums and, at the end of a step, writes its record and stages the
+// next step's threshold table.  The host never has to read anything back
+// between sweeps, and every launch of a schedule has the same arguments.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "isf_tiles.h"
+
+namespace isf {
+
+template <int TX, int TY, int RY>
+__global__ __launch_bounds__(TX *TY) void k_phase_i8(LatDev L, uint32_t sigma) {
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh, run_sh;
+    stage_film(L, tab, &t_sh, &run_sh);
+    int dM = 0, dE = 0, acc = 0;
+    phase_tile_i8<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
+    const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    finish_block<TX * TY>(L, dM, dE, acc, blin, gridDim.x * gridDim.y * gridDim.z, sigma == 3);
+}
+
+// Batched: one launch covers the same sublattice of many films.  Block b
+// belongs to the film whose block range contains it.
+template <int TX, int TY, int RY>
+__global__ __launch_bounds__(TX *TY) void k_phase_i8_batch(const BatchEntry *__restrict__ ents, uint32_t n_ents,
+                                                           uint32_t sigma) {
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh, run_sh;
+    const uint32_t b = blockIdx.x;
+    const BatchEntry &e = ents[find_entry(ents, n_ents, b)];
+    const LatDev &L = e.lat;
+    if (!stage_film(L, tab, &t_sh, &run_sh))
+        return;  // this film's schedule is finished; uniform across the block
+    const uint32_t bl = b - e.block_begin;
+    const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
+    const uint32_t by = byz % e.nby, bz = byz / e.nby;
+    int dM = 0, dE = 0, acc = 0;
+    phase_tile_i8<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
+    finish_block<TX * TY>(L, dM, dE, acc, bl, e.nbx * e.nby * e.nbz, sigma == 3);
+}
+
+// --------------------------------------------------------------------------
+// Start: occupied sites get +1, -1, or +1 iff their INIT draw is below 2^31
+// (counter word 3 = sigma + 4, sweep word 0).  Vacancies keep the byte 1.
+__global__ void k_init_i8(LatDev L, int32_t mode) {
+    const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    if (d >= L.nd)
+        return;
+    uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
+    const size_t idx = ((size_t)(z + 1) * L.Y + y) * L.nd + d;
+    const uint32_t A = P[idx];
+    const uint32_t occ = ~A & 0x01010101u;
+    if (!occ)
+        return;
+    uint32_t v;
+    if (mode == ISF_INIT_UP) {
+        v = A | (occ << 1);          // 0 -> 2 on occupied bytes
+        v &= ~(occ);                 // clear bit 0 (already 0 on occupied)
+    } else if (mode == ISF_INIT_DOWN) {
+        v = A & ~(occ * 3u);         // occupied bytes -> 0
+    } else {
+        const uint32_t sigma = (y & 1u) + 2u * (z & 1u);
+        uint32_t u[4];
+        philox((z * L.Y + y) * L.nd + d, 0u, L.replica, sigma + 4u, L.key0, L.key1, u);
+        v = A;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if ((occ >> (8 * i)) & 1u) {
+                const uint32_t byte = u[i] < 0x80000000u ? 2u : 0u;
+                v = (v & ~(0xFFu << (8 * i))) | (byte << (8 * i));
+            }
+        }
+    }
+    P[idx] = v;
+}
+
+// Full recount of M, sum_i s_i n_i, occupied sites and occupied-neighbour
+// pairs, from the spins alone.  out[4] must be zero on entry.
+__global__ void k_recount_i8(LatDev L, int64_t *out) {
+    const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    int m = 0, sn = 0, no = 0, nb = 0;
+    if (d < L.nd) {
+        const bool left = (((y ^ z) & 1u) == 0);
+        const Nb r = gather_i8<true>(reinterpret_cast<const uint32_t *>(L.spins), L.Y, L.nd, y, z, d, left);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = (r.self >> (8 * i)) & 0xFF;
+            if (b == 1)
+                continue;
+            const int s = b - 1;
+            const int n = (int)((r.sum >> (8 * i)) & 0xFFu) - 12;
+            m += s;
+            sn += s * n;
+            no += 1;
+            nb += (int)((r.occsum >> (8 * i)) & 0xFFu);
+        }
+    }
+    m = wave_sum(m);
+    sn = wave_sum(sn);
+    no = wave_sum(no);
+    nb = wave_sum(nb);
+    if ((threadIdx.x & 63) == 0 && (no | m | sn | nb)) {
+        aadd(&out[0], (int64_t)m);
+        aadd(&out[1], (int64_t)sn);
+        aadd(&out[2], (int64_t)no);
+        aadd(&out[3], (int64_t)nb);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Host-side launchers.
+
+#define ISF_TILINGS(X) X(64, 4, 1) X(64, 4, 2) X(64, 4, 4) X(32, 8, 1) X(32, 8, 2) X(32, 8, 4) X(16, 16, 1) X(16, 16, 2) X(16, 16, 4)
+
+static void grid_i8(const LatDev &L, const Tiling &tl, uint32_t sigma, dim3 &g) {
+    const uint32_t half = L.Y / 2;
+    const uint32_t nz = (L.Z + 1) / 2;  // active planes of pz = 0; pz = 1 has Z/2, extra blocks exit
+    (void)sigma;
+    g.x = (L.nd + tl.tx - 1) / tl.tx;
+    g.y = (half + tl.ty * tl.ry - 1) / (tl.ty * tl.ry);
+    g.z = nz;
+}
+
+hipError_t launch_phase_i8(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s) {
+    dim3 g;
+    grid_i8(L, tl, sigma, g);
+#define X(a, b, c)                                                                  \
+    if (tl.tx == a && tl.ty == b && tl.ry == c) {                                   \
+        hipLaunchKernelGGL((k_phase_i8<a, b, c>), g, dim3(a * b), 0, s, L, sigma); \
+        return hipGetLastError();                                                   \
+    }
+    ISF_TILINGS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+void batch_grid_i8(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz) {
+    dim3 g;
+    grid_i8(L, tl, 0, g);
+    nbx = g.x;
+    nby = g.y;
+    nbz = g.z;
+}
+
+hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, uint32_t total_blocks,
+                                 const Tiling &tl, uint32_t sigma, hipStream_t s) {
+#define X(a, b, c)                                                                                        \
+    if (tl.tx == a && tl.ty == b && tl.ry == c) {                                                         \
+        hipLaunchKernelGGL((k_phase_i8_batch<a, b, c>), dim3(total_blocks), dim3(a * b), 0, s, ents_dev, \
+                           n_ents, sigma);                                                                \
+        return hipGetLastError();                                                                         \
+    }
+    ISF_TILINGS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+bool tiling_supported(const Tiling &tl) {
+#define X(a, b, c) \
+    if (tl.tx == a && tl.ty == b && tl.ry == c) return true;
+    ISF_TILINGS(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s) {
+    dim3 g((L.nd + 255) / 256, L.Y, L.Z);
+    hipLaunchKernelGGL(k_init_i8, g, dim3(256), 0, s, L, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s) {
+    dim3 g((L.nd + 255) / 256, L.Y, L.Z);
+    hipLaunchKernelGGL(k_recount_i8, g, dim3(256), 0, s, L, out);
+    return hipGetLastError();
+}
+
+}  // namespace isf

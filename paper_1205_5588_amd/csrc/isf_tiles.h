@@ -1,0 +1,264 @@
+// Tile bodies of one sublattice phase, for both storage formats.  Shared by
+// the one-launch-per-phase kernels and the persistent batched kernel.
+#pragma once
+
+#include "isf_device.h"
+
+namespace isf {
+
+// ---------------------------------------------------------------------------
+// INT8 format (one byte per compact site; see isf_internal.h)
+
+// Bytes of a row shifted by one compact column: for delta = -1 the dword of
+// columns (4d-1 .. 4d+2), for delta = +1 the dword of columns (4d+1 .. 4d+4).
+__device__ __forceinline__ uint32_t shifted(bool left, uint32_t cur, uint32_t other) {
+    return left ? __builtin_amdgcn_alignbyte(cur, other, 3) : __builtin_amdgcn_alignbyte(other, cur, 1);
+}
+
+// Sum of the 12 neighbour bytes of the 4 sites in dword d of row (y, z)
+// (INT8 format), plus the site dword itself.  Returns per byte n + 12.
+struct Nb {
+    uint32_t self;
+    uint32_t sum;     // per byte: sum of the 12 neighbour bytes
+    uint32_t occsum;  // per byte: number of occupied neighbours (only if wanted)
+};
+
+template <bool kOcc>
+__device__ __forceinline__ Nb gather_i8(const uint32_t *P, uint32_t Y, uint32_t nd, uint32_t y, uint32_t z,
+                                        uint32_t d, bool left) {
+    const uint32_t ym = y == 0 ? Y - 1 : y - 1;
+    const uint32_t yp = y + 1 == Y ? 0 : y + 1;
+    const uint32_t dd = left ? (d == 0 ? nd - 1 : d - 1) : (d + 1 == nd ? 0 : d + 1);
+    const size_t p0 = (size_t)z * Y;  // padded plane index of z-1
+    const size_t p1 = p0 + Y;         // plane z
+    const size_t p2 = p1 + Y;         // plane z+1
+    const size_t r_ym = (p1 + ym) * nd, r_yp = (p1 + yp) * nd;
+    const size_t r_zm = (p0 + y) * nd, r_zp = (p2 + y) * nd;
+    const uint32_t a1 = P[r_ym + d], a1o = P[r_ym + dd];
+    const uint32_t a2 = P[r_yp + d], a2o = P[r_yp + dd];
+    const uint32_t b1 = P[r_zm + d], b1o = P[r_zm + dd];
+    const uint32_t b2 = P[r_zp + d], b2o = P[r_zp + dd];
+    const uint32_t c1 = P[(p0 + ym) * nd + d];
+    const uint32_t c2 = P[(p0 + yp) * nd + d];
+    const uint32_t c3 = P[(p2 + ym) * nd + d];
+    const uint32_t c4 = P[(p2 + yp) * nd + d];
+    Nb r;
+    r.self = P[(p1 + y) * nd + d];
+    const uint32_t s1 = shifted(left, a1, a1o), s2 = shifted(left, a2, a2o);
+    const uint32_t s3 = shifted(left, b1, b1o), s4 = shifted(left, b2, b2o);
+    r.sum = ((a1 + a2) + (b1 + b2)) + ((s1 + s2) + (s3 + s4)) + ((c1 + c2) + (c3 + c4));
+    if (kOcc) {
+        const uint32_t m = 0x01010101u;
+        r.occsum = ((~a1 & m) + (~a2 & m) + (~b1 & m) + (~b2 & m)) + ((~s1 & m) + (~s2 & m) + (~s3 & m) + (~s4 & m)) +
+                   ((~c1 & m) + (~c2 & m) + (~c3 & m) + (~c4 & m));
+    } else {
+        r.occsum = 0;
+    }
+    return r;
+}
+
+// --------------------------------------------------------------------------
+// One tile of one sublattice phase (INT8 format).
+template <int TX, int TY, int RY>
+__device__ __forceinline__ void phase_tile_i8(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
+                                              const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
+    const uint32_t py = sigma & 1u, pz = sigma >> 1;
+    const uint32_t z = 2 * bz + pz;
+    const uint32_t tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const uint32_t d = bx * TX + tx;
+    if (z >= L.Z || d >= L.nd)
+        return;
+    const uint32_t Y = L.Y, nd = L.nd, half = Y >> 1;
+    uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
+    const bool left = ((py ^ pz) == 0);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const uint32_t yi = (by * RY + r) * TY + ty;
+        if (yi >= half)
+            break;
+        const uint32_t y = 2 * yi + py;
+        const Nb nb = gather_i8<false>(P, Y, nd, y, z, d, left);
+        const uint32_t A = nb.self;
+        const uint32_t occ = ~A & 0x01010101u;  // 1 in each byte of an occupied site
+        if (!occ)
+            continue;
+        uint32_t u[4];
+        philox((z * Y + y) * nd + d, t, L.replica, sigma, L.key0, L.key1, u);
+        uint32_t F = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t b = (A >> (8 * i)) & 0xFFu;
+            const uint32_t s = (nb.sum >> (8 * i)) & 0xFFu;
+            if (b != 1u) {
+                const uint32_t thr = tab[s + (b >> 1) * 25u];
+                if (thr == kSentinel || u[i] < thr) {
+                    F |= 2u << (8 * i);
+                    dM += 2 - 2 * (int)b;
+                    dE += 2 * ((int)b - 1) * ((int)s - 12);
+                    acc += 1;
+                }
+            }
+        }
+        if (F)
+            P[((size_t)(z + 1) * Y + y) * nd + d] = A ^ F;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// BITPACK format (spin bit + occupancy bit per site)
+
+// Column j of a row shifted by delta: bit i of the result is column 32w+i+delta.
+__device__ __forceinline__ uint32_t shift_bits(bool left, uint32_t cur, uint32_t other) {
+    return left ? ((cur << 1) | (other >> 31)) : ((cur >> 1) | (other << 31));
+}
+
+// 4-bit bit-sliced counter: add one bit per site (counts stay <= 12).
+struct Cnt4 {
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    __device__ __forceinline__ void add(uint32_t x) {
+        const uint32_t k0 = c0 & x;
+        c0 ^= x;
+        const uint32_t k1 = c1 & k0;
+        c1 ^= k0;
+        const uint32_t k2 = c2 & k1;
+        c2 ^= k1;
+        c3 ^= k2;
+    }
+};
+
+struct NbBits {
+    uint32_t spin, occ;
+    Cnt4 up, vac;
+};
+
+// Neighbour counts of the 32 sites in word w of row (y, z).
+__device__ __forceinline__ NbBits gather_bp(const uint32_t *P, uint32_t Y, uint32_t nw, uint32_t y, uint32_t z,
+                                            uint32_t w, bool left) {
+    const uint32_t ym = y == 0 ? Y - 1 : y - 1;
+    const uint32_t yp = y + 1 == Y ? 0 : y + 1;
+    const uint32_t wo = left ? (w == 0 ? nw - 1 : w - 1) : (w + 1 == nw ? 0 : w + 1);
+    const size_t p0 = (size_t)z * Y, p1 = p0 + Y, p2 = p1 + Y;
+    auto row = [&](size_t plane, uint32_t yy) { return P + (plane + yy) * 2 * nw; };
+    NbBits r;
+    const uint32_t *self = row(p1, y);
+    r.spin = self[w];
+    r.occ = self[nw + w];
+    const uint32_t *sh_rows[4] = {row(p1, ym), row(p1, yp), row(p0, y), row(p2, y)};
+    const uint32_t *st_rows[4] = {row(p0, ym), row(p0, yp), row(p2, ym), row(p2, yp)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t *q = sh_rows[k];
+        const uint32_t s = q[w], so = q[wo], o = q[nw + w], oo = q[nw + wo];
+        r.up.add(s);
+        r.vac.add(~o);
+        r.up.add(shift_bits(left, s, so));
+        r.vac.add(~shift_bits(left, o, oo));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t *q = st_rows[k];
+        r.up.add(q[w]);
+        r.vac.add(~q[nw + w]);
+    }
+    return r;
+}
+
+// Bit-sliced 6-bit table index idx = 2U + D + 25 s (idx <= 49).
+struct Idx6 {
+    uint32_t b[6];
+};
+
+__device__ __forceinline__ Idx6 table_index(const Cnt4 &U, const Cnt4 &D, uint32_t s) {
+    // S = (U << 1) + D, 5 bits
+    uint32_t S[5];
+    S[0] = D.c0;
+    uint32_t c = U.c0 & D.c1;
+    S[1] = U.c0 ^ D.c1;
+    uint32_t t = U.c1 ^ D.c2;
+    S[2] = t ^ c;
+    c = (U.c1 & D.c2) | (c & t);
+    t = U.c2 ^ D.c3;
+    S[3] = t ^ c;
+    c = (U.c2 & D.c3) | (c & t);
+    S[4] = U.c3 ^ c;  // S <= 24 < 32: no carry out
+    // + 25 s: 25 = 0b11001, add s at bits 0, 3 and 4
+    Idx6 r;
+    uint32_t k = S[0] & s;
+    r.b[0] = S[0] ^ s;
+    r.b[1] = S[1] ^ k;
+    k = S[1] & k;
+    r.b[2] = S[2] ^ k;
+    k = S[2] & k;
+    t = S[3] ^ s;
+    r.b[3] = t ^ k;
+    k = (S[3] & s) | (k & t);
+    t = S[4] ^ s;
+    r.b[4] = t ^ k;
+    k = (S[4] & s) | (k & t);
+    r.b[5] = k;
+    return r;
+}
+
+template <int TX, int TY, int RY>
+__device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
+                                              const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
+    const uint32_t py = sigma & 1u, pz = sigma >> 1;
+    const uint32_t z = 2 * bz + pz;
+    const uint32_t tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const uint32_t w = bx * TX + tx;
+    const uint32_t nw = L.nd;
+    if (z >= L.Z || w >= nw)
+        return;
+    const uint32_t Y = L.Y, half = Y >> 1;
+    uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
+    const bool left = ((py ^ pz) == 0);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const uint32_t yi = (by * RY + r) * TY + ty;
+        if (yi >= half)
+            break;
+        const uint32_t y = 2 * yi + py;
+        const NbBits nb = gather_bp(P, Y, nw, y, z, w, left);
+        if (!nb.occ)
+            continue;
+        const Idx6 ix = table_index(nb.up, nb.vac, nb.spin);
+        // Philox groups: compact index k = (z Y + y) W + 32 w + i, group k >> 2
+        const uint32_t g0 = ((z * Y + y) * nw + w) * 8u;
+        uint32_t F = 0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            if (!((nb.occ >> (4 * g)) & 0xFu))
+                continue;
+            uint32_t u[4];
+            philox(g0 + g, t, L.replica, sigma, L.key0, L.key1, u);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * g + j;
+                const uint32_t idx = ((ix.b[0] >> i) & 1u) | (((ix.b[1] >> i) & 1u) << 1) |
+                                     (((ix.b[2] >> i) & 1u) << 2) | (((ix.b[3] >> i) & 1u) << 3) |
+                                     (((ix.b[4] >> i) & 1u) << 4) | (((ix.b[5] >> i) & 1u) << 5);
+                const uint32_t thr = tab[idx];
+                const bool ok = ((nb.occ >> i) & 1u) && (thr == kSentinel || u[j] < thr);
+                F |= (uint32_t)ok << i;
+            }
+        }
+        if (F) {
+            const uint32_t fu = F & nb.spin, fd = F & ~nb.spin;
+            const int cu = __popc(fu), cd = __popc(fd);
+            dM += 2 * (cd - cu);
+            acc += cu + cd;
+            // sum of S = 2U + D over flipped sites, per direction: E changes by 2 s (S - 12)
+            const uint32_t U0 = nb.up.c0, U1 = nb.up.c1, U2 = nb.up.c2, U3 = nb.up.c3;
+            const uint32_t D0 = nb.vac.c0, D1 = nb.vac.c1, D2 = nb.vac.c2, D3 = nb.vac.c3;
+            const int su = 2 * (__popc(U0 & fu) + 2 * __popc(U1 & fu) + 4 * __popc(U2 & fu) + 8 * __popc(U3 & fu)) +
+                 (__popc(D0 & fu) + 2 * __popc(D1 & fu) + 4 * __popc(D2 & fu) + 8 * __popc(D3 & fu));
+            const int sd = 2 * (__popc(U0 & fd) + 2 * __popc(U1 & fd) + 4 * __popc(U2 & fd) + 8 * __popc(U3 & fd)) +
+                 (__popc(D0 & fd) + 2 * __popc(D1 & fd) + 4 * __popc(D2 & fd) + 8 * __popc(D3 & fd));
+            dE += 2 * (su - 12 * cu) - 2 * (sd - 12 * cd);
+            P[((size_t)(z + 1) * Y + y) * 2 * nw + w] = nb.spin ^ F;
+        }
+    }
+}
+
+}  // namespace isf

@@ -1,0 +1,302 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Spins and every integer record field (M, E_bond, sums, accepted flips) must be
+identical; derived per-spin values are compared at tolerance 0 by computing
+them the same way on both sides.  Cases cover several tiles and ragged tails,
+both storage formats, every launch shape, graph and plain launches, the
+degenerate films (one layer, empty, full), and the full-size workloads on a
+prefix of their schedules.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def isf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1205_5588_amd import lattice
+
+    return lattice
+
+
+def _pair(isf, h, Z, seed, replica=0, init=0, fmt=0, tuning=None):
+    g = isf.Lattice(h, Z, seed, replica=replica, init=init, fmt=fmt)
+    if tuning is not None:
+        g.set_tuning(*tuning)
+    o = cpu.Film(h, Z, seed, replica, init=init)
+    return g, o
+
+
+def _rand_h(shape, Z, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, Z + 1, size=shape).astype(np.uint8)
+
+
+def _assert_same(g, o, what=""):
+    np.testing.assert_array_equal(g.spins(), o.spins(), err_msg="spins " + what)
+    ob = g.observables()
+    st = o.state()
+    assert (ob["M"], ob["E"], ob["n_occ"], ob["n_bonds"], ob["sweeps"]) == st, (what, ob, st)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("init", [0, 1, 2])
+def test_start_state(isf, fmt, init):
+    X = 128 if fmt else 72
+    h = _rand_h((38, X), 5, 1 + init)
+    g, o = _pair(isf, h, 5, 0xDEADBEEF12345, replica=7, init=init, fmt=fmt)
+    _say("start", fmt, init)
+    _assert_same(g, o, "start")
+
+
+SHAPES = [(72, 38, 5), (64, 64, 3), (136, 20, 4), (8, 4, 1), (264, 10, 2)]
+
+
+@pytest.mark.parametrize("X,Y,Z", SHAPES)
+def test_small_films_schedule(isf, X, Y, Z):
+    h = _rand_h((Y, X), Z, X + Y + Z)
+    steps = [(2.5, 30, 3, 0), (0.8, -45, 4, 1), (9.0, 0, 2, 0), (4.0, -7, 5, 2), (1e-3, 241, 1, 0)]
+    g, o = _pair(isf, h, Z, 987654321, replica=3, init=2)
+    _say("schedule", X, Y, Z)
+    rg = g.run_schedule(steps)
+    ro = np.array([o.run(*s).as_tuple() for s in steps], dtype=np.int64)
+    np.testing.assert_array_equal(rg, ro)
+    _assert_same(g, o)
+
+
+TILINGS = [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
+           (16, 16, 4)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS)
+def test_every_tiling_same_trajectory(isf, tiling):
+    X, Y, Z = 328, 46, 6   # 41 dwords per row, 23 active rows: ragged in both tile directions
+    h = _rand_h((Y, X), Z, 5)
+    g, o = _pair(isf, h, Z, 42, replica=1, init=2, tuning=tiling + (False,))
+    _say("tiling", tiling)
+    hs = [60, 20, -20, -60, 0, 40]
+    np.testing.assert_array_equal(g.ramp_field(3.0, hs, 6), cpu.hysteresis(o, 3.0, hs, 6))
+    _assert_same(g, o)
+
+
+@pytest.mark.parametrize("tiling", [(64, 4, 1), (32, 8, 2), (16, 16, 1)])
+def test_bitpack_matches_oracle(isf, tiling):
+    X, Y, Z = 192, 22, 7   # 3 words per row
+    h = _rand_h((Y, X), Z, 11)
+    g, o = _pair(isf, h, Z, 5555, replica=2, init=2, fmt=1, tuning=tiling + (False,))
+    _say("bitpack", tiling)
+    steps = [(2.0, 25, 4, 0), (6.0, -13, 3, 1), (0.5, 0, 3, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_graph_replay_matches_plain(isf):
+    X, Y, Z = 256, 64, 4
+    h = _rand_h((Y, X), Z, 21)
+    a = isf.Lattice(h, Z, 77, init=0)
+    b = isf.Lattice(h, Z, 77, init=0)
+    a.set_tuning(64, 4, 2, True)
+    b.set_tuning(64, 4, 2, False)
+    _say("graph")
+    steps = [(3.5, 40, 150, 10), (3.5, -40, 130, 0), (2.0, 0, 64, 0)]
+    ra = a.run_schedule(steps)
+    rb = b.run_schedule(steps)
+    np.testing.assert_array_equal(ra, rb)
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    o = cpu.Film(h, Z, 77)
+    np.testing.assert_array_equal(ra, np.array([o.run(*s).as_tuple() for s in steps]))
+
+
+def test_degenerate_films(isf):
+    _say("degenerate")
+    # empty film: nothing occupied
+    h = np.zeros((8, 16), dtype=np.uint8)
+    g, o = _pair(isf, h, 3, 1, init=2)
+    np.testing.assert_array_equal(g.run_sweeps(2.0, 10, 5), o.run(2.0, 10, 5).as_tuple())
+    assert g.observables()["n_occ"] == 0
+    # full film
+    h = np.full((16, 32), 4, dtype=np.uint8)
+    g, o = _pair(isf, h, 4, 2, init=1)
+    np.testing.assert_array_equal(g.run_sweeps(7.0, -3, 9, 2), o.run(7.0, -3, 9, 2).as_tuple())
+    _assert_same(g, o)
+    # one layer (sublattices 2, 3 empty), square lattice
+    h = np.ones((32, 64), dtype=np.uint8)
+    g, o = _pair(isf, h, 1, 3, init=2)
+    np.testing.assert_array_equal(g.run_sweeps(2.2, 0, 20), o.run(2.2, 0, 20).as_tuple())
+    _assert_same(g, o)
+    # zero sweeps
+    r = g.run_sweeps(2.2, 0, 0)
+    assert r[0] == g.observables()["M"] and r[2] == 0
+
+
+def test_extreme_parameters(isf):
+    h = _rand_h((20, 40), 3, 9)
+    g, o = _pair(isf, h, 3, 123, init=2)
+    _say("extreme")
+    steps = [(1e-3, 1, 3, 0), (1e6, 0, 3, 0), (1e-3, -241, 2, 0), (1.0, 200000, 1, 0), (1.0, -200000, 1, 0),
+             (0.31, 17, 3, 3)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_invalid_arguments_raise(isf):
+    from paper_1205_5588_amd import IsfError
+
+    h = _rand_h((8, 16), 2, 3)
+    g = isf.Lattice(h, 2, 1)
+    for bad in [(0.0, 0, 1, 0), (float("nan"), 0, 1, 0), (1.0, 300000, 1, 0), (1.0, 0, 0, 0), (1.0, 0, 2, 3)]:
+        with pytest.raises(IsfError):
+            g.run_schedule([bad])
+    with pytest.raises(IsfError):
+        isf.Lattice(np.full((8, 16), 3, dtype=np.uint8), 2, 1)   # h > Z
+    with pytest.raises(IsfError):
+        isf.Lattice(np.ones((8, 12), dtype=np.uint8), 2, 1)      # X % 8 != 0
+    with pytest.raises(IsfError):
+        g.set_tuning(128, 2, 1, False)
+    with pytest.raises(IsfError):
+        g.set_spins(np.full((2, 8, 16), 5, dtype=np.int8), 0)
+
+
+def test_incremental_equals_recount_and_resume(isf):
+    X, Y, Z = 96, 48, 5
+    h = _rand_h((Y, X), Z, 33)
+    g = isf.Lattice(h, Z, 999, replica=4, init=2)
+    _say("recount/resume")
+    for hn in (50, -10, -50, 20):
+        g.run_sweeps(3.0, hn, 7)
+        ob = g.observables()
+        assert g.recount() == (ob["M"], ob["E"])
+    # checkpoint, restore into a new handle, continue == uninterrupted
+    snap, t = g.spins(), g.observables()["sweeps"]
+    r1 = g.run_schedule([(2.5, -30, 11, 0), (2.5, 30, 5, 1)])
+    g2 = isf.Lattice(h, Z, 999, replica=4, init=0)
+    g2.set_spins(snap, t)
+    r2 = g2.run_schedule([(2.5, -30, 11, 0), (2.5, 30, 5, 1)])
+    np.testing.assert_array_equal(r1, r2)
+    np.testing.assert_array_equal(g.spins(), g2.spins())
+
+
+def test_field_reversal_symmetry_gpu(isf):
+    h = _rand_h((24, 64), 4, 44)
+    a = isf.Lattice(h, 4, 31337, init=2)
+    b = isf.Lattice(h, 4, 31337, init=0)
+    b.set_spins(-a.spins(), 0)
+    _say("symmetry")
+    hs = [40, 10, -20, -60, 0, 33, -1]
+    ra = a.ramp_field(2.5, hs, 3)
+    rb = b.ramp_field(2.5, [-v for v in hs], 3)
+    np.testing.assert_array_equal(b.spins(), -a.spins())
+    np.testing.assert_array_equal(rb[:, [0, 2]], -ra[:, [0, 2]])
+    np.testing.assert_array_equal(rb[:, [1, 3, 4, 5]], ra[:, [1, 3, 4, 5]])
+
+
+# ------------------------------------------------------------------ full-size workloads
+def test_config_plain_hysteresis_small_full(isf):
+    from isf_workloads import config_plain_hysteresis_small
+
+    c = config_plain_hysteresis_small()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    _say("c1 full ramp")
+    rg = g.ramp_field(c.T, c.h_nums, c.sweeps_per_step)
+    ro = cpu.hysteresis(o, c.T, c.h_nums, c.sweeps_per_step)
+    np.testing.assert_array_equal(rg, ro)
+    _assert_same(g, o)
+    # derived per-spin magnetisation, same arithmetic on both sides: tolerance 0
+    n = g.observables()["n_occ"]
+    assert [float(r[0]) / float(n) for r in rg] == [float(r[0]) / float(n) for r in ro]
+
+
+def test_config_plain_tscan_prefix(isf):
+    from isf_workloads import config_plain_tscan
+
+    c = config_plain_tscan()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    _say("c2 first temperatures, full film")
+    temps = c.temps[:2]
+    sw, dc = 250, 50
+    rg = g.temperature_scan(temps, sw, dc)
+    ro = cpu.tscan(o, temps, sw, dc)
+    np.testing.assert_array_equal(rg, ro)
+    _assert_same(g, o)
+    n = g.observables()["n_occ"]
+    kept = sw - dc
+    assert [float(r[3]) / (float(kept) * float(n)) for r in rg] == [float(r[3]) / (float(kept) * float(n)) for r in ro]
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_config_plain_hysteresis_large_prefix(isf, fmt):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init, fmt=fmt)
+    _say("c3 prefix fmt", fmt)
+    hs = c.h_nums[:1]
+    rg = g.ramp_field(c.T, hs, 12)
+    ro = cpu.hysteresis(o, c.T, hs, 12)
+    np.testing.assert_array_equal(rg, ro)
+    _assert_same(g, o)
+
+
+# ------------------------------------------------------------------ batches
+def _batch_films(isf, fmt=0):
+    rng = np.random.default_rng(77)
+    films = []
+    for i, (X, Y, Z) in enumerate([(64, 40, 3), (192, 64, 5), (128, 16, 2), (320, 24, 6), (64, 64, 1)]):
+        h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+        T = float(rng.uniform(1.0, 9.0))
+        n_steps = 3 + i
+        hs = [int(v) for v in rng.integers(-60, 61, size=n_steps)]
+        sched = [(T, hv, int(rng.integers(2, 7)), 0) for hv in hs]
+        films.append((h, Z, 1000 + i, i, sched))
+    return films
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_batched_equals_alone_and_oracle(isf, mode, fmt):
+    films = _batch_films(isf)
+    if fmt == 1:
+        films = [(np.tile(h, (1, 2))[:, : max(64, (h.shape[1] // 64) * 64)], Z, s, r, sc)
+                 for (h, Z, s, r, sc) in films]
+    _say("batch mode", mode, "fmt", fmt)
+    lats = [isf.Lattice(h, Z, s, replica=r, init=2, fmt=fmt) for (h, Z, s, r, sc) in films]
+    b = isf.Batch(len(lats))
+    recs = b.run(lats, [f[4] for f in films], mode=mode)
+    for (h, Z, s, r, sc), lat, rec in zip(films, lats, recs):
+        o = cpu.Film(h, Z, s, r, init=2)
+        np.testing.assert_array_equal(rec, np.array([o.run(*st).as_tuple() for st in sc]))
+        np.testing.assert_array_equal(lat.spins(), o.spins())
+
+
+def test_batched_incremental_chunks(isf):
+    films = _batch_films(isf)
+    lats = [isf.Lattice(h, Z, s, replica=r, init=2) for (h, Z, s, r, sc) in films]
+    _say("batch chunks")
+    for lat, f in zip(lats, films):
+        lat.schedule_load(f[4])
+    b = isf.Batch(len(lats))
+    while any(l.remaining() for l in lats):
+        b.advance(lats, 3, mode=0)
+    b.sync()
+    for (h, Z, s, r, sc), lat in zip(films, lats):
+        o = cpu.Film(h, Z, s, r, init=2)
+        np.testing.assert_array_equal(lat.records(), np.array([o.run(*st).as_tuple() for st in sc]))

@@ -1,0 +1,101 @@
+"""Host-side checks of the HIP library (no GPU needed): it loads, exports
+every symbol include/isf.h declares, validates descriptions, and its
+threshold tables equal the oracle's for every (T, h_num) the workloads use."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import cpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1205_5588_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1205_5588_amd.build import build
+
+        build()
+    return _lib.load()
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "isf.h")).read()
+    return sorted(set(re.findall(r"\b(isf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 25
+    for s in syms:
+        assert hasattr(lib, s), s
+    from paper_1205_5588_amd import _lib
+
+    assert set(syms) == set(_lib.EXPORTS), set(syms) ^ set(_lib.EXPORTS)
+    assert lib.isf_abi_version() == 1
+
+
+def _bytes(lib, X, Y, Z, fmt=0, reserved=0):
+    from paper_1205_5588_amd._lib import Desc
+
+    d = Desc(X, Y, Z, 0, 0, fmt, reserved)
+    s = ctypes.c_uint64()
+    a = ctypes.c_uint64()
+    rc = lib.isf_lattice_bytes(ctypes.byref(d), ctypes.byref(s), ctypes.byref(a))
+    return rc, s.value, a.value
+
+
+def test_descriptor_validation(lib):
+    rc, s, a = _bytes(lib, 2048, 2048, 8)
+    assert rc == 0 and s == 10 * 2048 * 1024 and a > 0
+    rc, s, _ = _bytes(lib, 2048, 2048, 8, fmt=1)
+    assert rc == 0 and s == 10 * 2048 * 2 * 32 * 4
+    for bad in [(4, 8, 2), (12, 8, 2), (16, 6, 0), (16, 7, 2), (16, 2, 2), (16, 8, 65)]:
+        assert _bytes(lib, *bad)[0] == -1, bad
+    assert _bytes(lib, 32, 8, 2, fmt=1)[0] == -1      # BITPACK needs X % 64 == 0
+    assert _bytes(lib, 64, 8, 2, fmt=2)[0] == -1      # unknown format
+    assert _bytes(lib, 64, 8, 2, reserved=1)[0] == -1
+    assert b"Z=65" in lib.isf_last_error() or b"reserved" in lib.isf_last_error()
+
+
+def test_threshold_validation(lib):
+    out = np.zeros((2, 25), dtype=np.uint32)
+    for T in (0.0, -1.0, float("inf"), float("nan"), 2e6):
+        assert lib.isf_threshold_table(T, 0, out.ctypes.data) == -1
+    assert lib.isf_threshold_table(1.0, 200001, out.ctypes.data) == -1
+    assert lib.isf_threshold_table(1.0, 200000, out.ctypes.data) == 0
+
+
+def _workload_pairs():
+    from isf_workloads import (batched_films, config_plain_hysteresis_large, config_plain_hysteresis_small,
+                               config_plain_tscan, serving_requests)
+
+    pairs = set()
+    for c in (config_plain_hysteresis_small(), config_plain_hysteresis_large()):
+        pairs |= {(c.T, h) for h in c.h_nums}
+    pairs |= {(T, 0) for T in config_plain_tscan().temps}
+    reps, _, hn, _ = batched_films()
+    for r in reps[::16]:
+        pairs |= {(r.T, h) for h in hn}
+    for q in serving_requests(max_requests=40):
+        if q.kind == "hysteresis":
+            pairs |= {(q.T, h) for h in q.h_nums[::10]}
+        else:
+            pairs |= {(T, 0) for T in q.temps}
+    pairs |= {(1e-3, 1), (1e-3, 241), (50.0, 0), (1e6, -200000)}
+    return sorted(pairs)
+
+
+def test_threshold_tables_equal_oracle(lib, oracle_lib):
+    pairs = _workload_pairs()
+    assert len(pairs) > 1000
+    out = np.zeros((2, 25), dtype=np.uint32)
+    for T, h in pairs:
+        assert lib.isf_threshold_table(float(T), int(h), out.ctypes.data) == 0
+        np.testing.assert_array_equal(out, cpu.threshold_table(T, h), err_msg=str((T, h)))
