@@ -76,6 +76,115 @@ def roofline_int8(lat, cfg, n_sweeps=40):
             "bytes_per_launch": int(bytes_per_launch)}
 
 
+def tune_plain(cfg, h, fmt):
+    from paper_1205_5588_amd.autotune import tune_lattice
+    from paper_1205_5588_amd.lattice import Lattice
+
+    res = tune_lattice(lambda: Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init, fmt=fmt), fmt, cfg.T, cfg.h_nums[0],
+                       sweeps=48, warmup=4)
+    return res
+
+
+def bench_batched(args):
+    """The batched workload: 16 uneven films x 16 temperatures = 256 replicas, each
+    with its own ramp +5 -> -5 -> +5 (step 0.1, 20 sweeps per step)."""
+    import torch
+
+    from isf_workloads import batched_films
+    from paper_1205_5588_amd.autotune import tune_batch
+    from paper_1205_5588_amd.lattice import Batch, Lattice
+
+    reps, seed, hnums, spst = batched_films()
+    stream = torch.cuda.Stream()
+    sched = [[(r.T, hv, spst, 0) for hv in hnums] for r in reps]
+
+    def make():
+        return [Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
+
+    t0 = time.perf_counter()
+    tuned = tune_batch(make, lambda i: sched[i], 0, sweeps=6,
+                       candidates=[(64, 4, 1), (64, 4, 2), (32, 8, 2), (16, 16, 2)])
+    log("batch tuning %.1fs: best %s mode %d (%.3f ms/sweep)" % (time.perf_counter() - t0, tuned["tiling"],
+                                                                 tuned["mode"], tuned["ms_per_sweep"]))
+    lats = make()
+    for l in lats:
+        l.set_tuning(*tuned["tiling"], False)
+    n_occ = [l.observables()["n_occ"] for l in lats]
+    b = Batch(len(lats), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = b.run(lats, sched, mode=tuned["mode"])
+    dt = time.perf_counter() - t0
+    attempts = sum(n * len(hnums) * spst for n in n_occ)
+    out = {"value": round(attempts / dt, 1), "unit": "spin-flip attempts/s", "replicas": len(reps),
+           "sweeps_per_replica": len(hnums) * spst, "attempts": attempts, "seconds": round(dt, 4),
+           "mode": "persistent" if tuned["mode"] == 1 else "phase_launch", "tiling": tuned["tiling"],
+           "tuning": tuned["all"]}
+    # the same replicas one after another through the plain path (a sample, shortened schedule)
+    sample = list(range(0, len(reps), 16))
+    short = 10
+    plain_dt = 0.0   # run time only; film construction is excluded
+    att = 0
+    for i in sample:
+        r = reps[i]
+        l = Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream)
+        l.set_tuning(*tuned["tiling"], True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        l.run_schedule(sched[i][:short])
+        plain_dt += time.perf_counter() - ts
+        att += n_occ[i] * short * spst
+        l.close()
+    out["plain_same_replicas"] = {"value": round(att / max(plain_dt, 1e-9), 1),
+                                  "sample": "16 replicas (one per film), first %d field steps, run one after "
+                                            "another through the plain path with graph replay" % short}
+    del lats, b
+    return out
+
+
+def serving_inputs(args):
+    """Requests and their height maps, generated before the GPU is touched (the
+    height maps are the requests' payload, not server work)."""
+    import multiprocessing as mp
+
+    from isf_workloads import serving_requests
+
+    reqs = serving_requests(duration=args.serve_duration)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        heights = pool.map(_heights_of, [(q.X, q.Y, q.Z, q.sigma, q.seed) for q in reqs], chunksize=8)
+    log("serving: %d requests, height maps %.1fs" % (len(reqs), time.perf_counter() - t0))
+    return reqs, {q.rid: hh for q, hh in zip(reqs, heights)}
+
+
+def bench_serving(args, reqs, hmap):
+    """Poisson arrivals (50 req/s for the configured duration) of hysteresis and
+    temperature-scan jobs on films of 64^2..2048^2 x 1..10 layers."""
+    from paper_1205_5588_amd.serve import GpuExecutor, Job, Server
+
+    jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q), n_sweeps=q.n_sweeps, payload=q)
+            for q in reqs]
+    ex = GpuExecutor(max_slots=args.serve_slots, mode=args.serve_mode, heights_of=lambda q: hmap[q.rid])
+    srv = Server(ex, budget_bytes=int(args.serve_budget_gib * 2**30), max_slots=args.serve_slots,
+                 target_chunk_s=0.02, rate_estimate=2e11, max_chunk=64)
+    t0 = time.perf_counter()
+    stats = srv.run(jobs)
+    wall = time.perf_counter() - t0
+    s = stats.summary()
+    s["wall_s"] = round(wall, 2)
+    s["offered_attempts_per_s"] = round(s["attempts"] / args.serve_duration, 1)
+    s["mode"] = "persistent" if args.serve_mode == 1 else "phase_launch"
+    s["arrivals"] = "Poisson 50 req/s for %g s" % args.serve_duration
+    return s
+
+
+def _heights_of(a):
+    from isf_workloads import height_map
+
+    X, Y, Z, sig, seed = a
+    return height_map(X, Y, Z, sig, seed)
+
+
 def cpu_baseline(cfg, h, budget_s=15.0):
     from oracle import cpu
 
@@ -103,12 +212,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-duration", type=float, default=60.0)
+    ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--serve-mode", type=int, default=0)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
               "(replicas and requests shard across GPUs without communication; see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    serve_in = None
+    if not args.no_extra and not args.no_serve:
+        serve_in = serving_inputs(args)   # CPU only, before the GPU is initialised
 
     import torch
 
@@ -120,20 +239,36 @@ def main():
     h = cfg.heights()
     log("height map %.2fs" % (time.perf_counter() - t0))
 
-    lat, n_occ, sweeps, wall, gpu_ms, recs = bench_plain(cfg, h, 0, args.steps, args.warmup)
+    tuning = None
+    tune_info = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune_info = tune_plain(cfg, h, 0)
+        tuning = tuple(tune_info["tiling"]) + (tune_info["use_graph"],)
+        log("plain tuning %.1fs: %s" % (time.perf_counter() - t0, tune_info))
+    lat, n_occ, sweeps, wall, gpu_ms, recs = bench_plain(cfg, h, 0, args.steps, args.warmup, tuning)
     value = n_occ * sweeps / (gpu_ms * 1e-3)
     log("plain int8: %d steps, %d sweeps, %.3f s wall, %.3f ms gpu, %.3e attempts/s" %
         (args.steps, sweeps, wall, gpu_ms, value))
     roof = roofline_int8(lat, cfg)
     log("roofline:", roof)
+    del lat
 
-    extra = {}
+    extra = {"tuning": tune_info}
     if not args.no_extra:
-        lat_b, n_occ_b, sw_b, wall_b, gpu_ms_b, recs_b = bench_plain(cfg, h, 1, min(args.steps, 40), 2)
+        tb = None if args.no_tune else tune_plain(cfg, h, 1)
+        tbt = None if tb is None else tuple(tb["tiling"]) + (tb["use_graph"],)
+        lat_b, n_occ_b, sw_b, wall_b, gpu_ms_b, recs_b = bench_plain(cfg, h, 1, min(args.steps, 40), 2, tbt)
         extra["bitpack"] = {"value": round(n_occ_b * sw_b / (gpu_ms_b * 1e-3), 1),
-                            "unit": "spin-flip attempts/s", "steps": min(args.steps, 40)}
+                            "unit": "spin-flip attempts/s", "steps": min(args.steps, 40),
+                            "tiling": None if tb is None else tb["tiling"]}
         log("bitpack:", extra["bitpack"])
         del lat_b
+        extra["batched"] = bench_batched(args)
+        log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
+        if not args.no_serve:
+            extra["serving"] = bench_serving(args, *serve_in)
+            log("serving:", extra["serving"])
 
     cpu_base = None
     if not args.no_cpu:

@@ -67,7 +67,8 @@ enum { ISF_INIT_UP = 0, ISF_INIT_DOWN = 1, ISF_INIT_RANDOM = 2 };
  * Z: number of atomic layers (Section 3).
  *   INT8:    X a multiple of 8, X >= 8; Y even, Y >= 4; 1 <= Z <= 64.
  *   BITPACK: X a multiple of 64; same Y and Z limits.
- *   X * Y * Z / 2 <= 2^34 (stored sites). */
+ *   Y <= 65536, X * Y / 2 < 2^31 (bytes of one layer), X * Y * Z / 2 < 2^34
+ *   (stored sites). */
 typedef struct {
     uint32_t X, Y, Z;
     uint32_t replica;   /* Philox counter word 2 */

@@ -1,0 +1,145 @@
+"""Autotuner for the sweep kernels' launch shape.
+
+Searches the tile shape (dwords or words along a row x rows across), the
+rows handled per thread, graph replay vs plain launches, and for batches the
+execution mode (one launch per sublattice vs one persistent launch).  Every
+candidate runs the same schedule from the same start; a candidate whose
+records or spins differ from the first one is rejected (all shapes must give
+the identical trajectory, since draws are keyed by site and sweep only).
+
+Results are cached in JSON keyed by the film shape class.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from ._lib import BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8
+
+TILINGS = {
+    FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
+                  (16, 16, 4)],
+    FORMAT_BITPACK: [(64, 4, 1), (64, 4, 2), (32, 8, 1), (32, 8, 2), (16, 16, 1), (16, 16, 2)],
+}
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def shape_key(X: int, Y: int, Z: int, fmt: int) -> str:
+    return "%s:%dx%dx%d" % ("int8" if fmt == FORMAT_INT8 else "bitpack", X, Y, Z)
+
+
+def default_tiling(X: int, fmt: int) -> Tuple[int, int, int]:
+    """Heuristic for shapes not in the cache: widest tile that the row fills."""
+    per_row = X // 8 if fmt == FORMAT_INT8 else X // 64
+    if per_row >= 64:
+        return (64, 4, 2) if fmt == FORMAT_INT8 else (64, 4, 1)
+    if per_row >= 32:
+        return (32, 8, 2) if fmt == FORMAT_INT8 else (32, 8, 1)
+    return (16, 16, 2) if fmt == FORMAT_INT8 else (16, 16, 1)
+
+
+class TuningCache:
+    def __init__(self, path: str = CACHE_PATH):
+        self.path = path
+        self.data: Dict[str, dict] = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                self.data = json.load(fh)
+
+    def get(self, key: str) -> Optional[dict]:
+        return self.data.get(key)
+
+    def put(self, key: str, value: dict) -> None:
+        self.data[key] = value
+
+    def save(self, path: Optional[str] = None) -> None:
+        with open(path or self.path, "w") as fh:
+            json.dump(self.data, fh, indent=1, sort_keys=True)
+
+
+def lookup(X: int, Y: int, Z: int, fmt: int, cache: Optional[TuningCache] = None) -> Tuple[int, int, int, bool]:
+    cache = cache or TuningCache()
+    hit = cache.get(shape_key(X, Y, Z, fmt))
+    if hit:
+        return tuple(hit["tiling"]) + (bool(hit["use_graph"]),)
+    return default_tiling(X, fmt) + (True,)
+
+
+def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,
+                 warmup: int = 8, candidates: Optional[Sequence[Tuple[int, int, int]]] = None,
+                 graphs: Sequence[bool] = (True, False)) -> dict:
+    """Time every launch shape on fresh copies of one film; returns the best and all timings."""
+    import torch
+
+    cands = list(candidates or TILINGS[fmt])
+    ref_recs = ref_spins = None
+    timings: List[dict] = []
+    for tl in cands:
+        for g in graphs:
+            lat = make()
+            lat.set_tuning(tl[0], tl[1], tl[2], g)
+            lat.run_schedule([(T, h_num, warmup, 0)])
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(lat.stream)
+            recs = lat.run_schedule([(T, h_num, sweeps, 0)])
+            ev1.record(lat.stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            spins = lat.spins()
+            if ref_recs is None:
+                ref_recs, ref_spins = recs, spins
+            elif not (np.array_equal(recs, ref_recs) and np.array_equal(spins, ref_spins)):
+                raise AssertionError("launch shape %s graph=%s changed the trajectory" % (tl, g))
+            timings.append({"tiling": list(tl), "use_graph": g, "ms_per_sweep": ms / sweeps})
+            lat.close()
+            del lat
+    best = min(timings, key=lambda r: r["ms_per_sweep"])
+    return {"tiling": best["tiling"], "use_graph": best["use_graph"], "ms_per_sweep": best["ms_per_sweep"],
+            "all": timings}
+
+
+def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list], fmt: int,
+               sweeps: int = 8, candidates: Optional[Sequence[Tuple[int, int, int]]] = None,
+               modes: Sequence[int] = (BATCH_PHASE_LAUNCH, BATCH_PERSISTENT)) -> dict:
+    """Time launch shapes and batch modes on a batch of films (fresh copies per candidate)."""
+    import torch
+
+    from .lattice import Batch
+
+    cands = list(candidates or TILINGS[fmt])
+    timings = []
+    ref = None
+    for tl in cands:
+        for mode in modes:
+            lats = make_lats()
+            for i, l in enumerate(lats):
+                l.set_tuning(tl[0], tl[1], tl[2], False)
+                l.schedule_load(schedule_of(i))
+            b = Batch(len(lats))
+            b.advance(lats, 2, mode)  # warm-up sweeps
+            b.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.advance(lats, sweeps, mode)
+            b.sync()
+            dt = time.perf_counter() - t0
+            state = [l.observables() for l in lats]
+            key = [(s["M"], s["E"], s["sweeps"]) for s in state]
+            if ref is None:
+                ref = key
+            elif key != ref:
+                raise AssertionError("batch shape %s mode %d changed the trajectory" % (tl, mode))
+            timings.append({"tiling": list(tl), "mode": mode, "ms_per_sweep": dt * 1e3 / sweeps})
+            b.close()
+            for l in lats:
+                l.close()
+    best = min(timings, key=lambda r: r["ms_per_sweep"])
+    return {"tiling": best["tiling"], "mode": best["mode"], "ms_per_sweep": best["ms_per_sweep"], "all": timings}

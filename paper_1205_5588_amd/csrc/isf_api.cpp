@@ -25,6 +25,8 @@ hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, ui
 void batch_grid_i8(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz);
 bool tiling_supported(const Tiling &tl);
 hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
+hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
+hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s);
 hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s);
 
 hipError_t launch_phase_bp(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s);
@@ -79,9 +81,11 @@ int32_t validate_desc(const isf_desc *d) {
         return fail(ISF_EINVAL, "Y=%u must be even and >= 4", d->Y);
     if (d->Z < 1 || d->Z > 64)
         return fail(ISF_EINVAL, "Z=%u must be in [1, 64]", d->Z);
+    if (d->Y > 65536 || (uint64_t)d->X * d->Y / 2 >= (1ull << 31))
+        return fail(ISF_EINVAL, "plane too large: Y=%u must be <= 65536 and X*Y/2 < 2^31", d->Y);
     const uint64_t nc = (uint64_t)d->X * d->Y * d->Z / 2;
-    if (nc > (1ull << 34))
-        return fail(ISF_EINVAL, "film too large: %llu stored sites > 2^34", (unsigned long long)nc);
+    if (nc >= (1ull << 34))
+        return fail(ISF_EINVAL, "film too large: %llu stored sites >= 2^34", (unsigned long long)nc);
     return ISF_OK;
 }
 
@@ -169,13 +173,24 @@ int32_t launch_phase(const isf_lattice *lat, uint32_t sigma) {
     return ISF_OK;
 }
 
+int32_t launch_end(const isf_lattice *lat) {
+    hipError_t e = launch_sweep_end(lat->L, lat->stream);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "sweep-end launch failed: %s", hipGetErrorString(e));
+    return ISF_OK;
+}
+
 int32_t enqueue_sweeps_plain(const isf_lattice *lat, uint64_t n) {
-    for (uint64_t i = 0; i < n; ++i)
+    for (uint64_t i = 0; i < n; ++i) {
         for (uint32_t s = 0; s < 4; ++s) {
             int32_t rc = launch_phase(lat, s);
             if (rc)
                 return rc;
         }
+        int32_t rc = launch_end(lat);
+        if (rc)
+            return rc;
+    }
     return ISF_OK;
 }
 
@@ -726,12 +741,15 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
     for (auto &e : ev)
         HIP_TRY(hipEventCreate(&e));
     int32_t status = ISF_OK;
-    for (uint32_t i = 0; i < n && status == ISF_OK; ++i)
+    for (uint32_t i = 0; i < n && status == ISF_OK; ++i) {
         for (uint32_t s = 0; s < 4 && status == ISF_OK; ++s) {
             (void)hipEventRecord(ev[8 * i + 2 * s], lat->stream);
             status = launch_phase(lat, s);
             (void)hipEventRecord(ev[8 * i + 2 * s + 1], lat->stream);
         }
+        if (status == ISF_OK)
+            status = launch_end(lat);
+    }
     double sum[4] = {0, 0, 0, 0};
     if (status == ISF_OK) {
         lat->sched_enqueued += n;
@@ -889,7 +907,7 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
     HIP_TRY(hipMemcpyAsync(ents, b->staging, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipEventRecord(b->staged, b->stream));
     if (mode == ISF_BATCH_PHASE_LAUNCH) {
-        for (uint64_t sw = 0; sw < sweeps; ++sw)
+        for (uint64_t sw = 0; sw < sweeps; ++sw) {
             for (uint32_t s = 0; s < 4; ++s) {
                 hipError_t e = format == ISF_FORMAT_INT8
                                    ? launch_phase_i8_batch(ents, m, blocks, tl, s, b->stream)
@@ -897,11 +915,20 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
                 if (e != hipSuccess)
                     return fail(ISF_EHIP, "batched phase launch: %s", hipGetErrorString(e));
             }
+            hipError_t e = launch_sweep_end_batch(ents, m, b->stream);
+            if (e != hipSuccess)
+                return fail(ISF_EHIP, "batched sweep-end launch: %s", hipGetErrorString(e));
+        }
     } else {
-        uint32_t grid = 0;
-        hipError_t e = launch_persistent(ents, m, blocks, format, tl, (uint32_t)sweeps, barrier, b->stream, &grid);
-        if (e != hipSuccess)
-            return fail(ISF_EHIP, "persistent launch: %s", hipGetErrorString(e));
+        // chunks keep the barrier's arrival counter (sweeps x 5 x grid) far below 2^32
+        for (uint64_t done = 0; done < sweeps;) {
+            const uint32_t chunk = (uint32_t)std::min<uint64_t>(sweeps - done, 2048);
+            uint32_t grid = 0;
+            hipError_t e = launch_persistent(ents, m, blocks, format, tl, chunk, barrier, b->stream, &grid);
+            if (e != hipSuccess)
+                return fail(ISF_EHIP, "persistent launch: %s", hipGetErrorString(e));
+            done += chunk;
+        }
         b->persistent_used = true;
     }
     for (uint32_t i = 0; i < n; ++i) {

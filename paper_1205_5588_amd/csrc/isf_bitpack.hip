@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "isf_tiles.h"
 
 namespace isf {
@@ -21,11 +23,11 @@ template <int TX, int TY, int RY>
 __global__ __launch_bounds__(TX *TY) void k_phase_bp(LatDev L, uint32_t sigma) {
     __shared__ uint32_t tab[kTableWords];
     __shared__ uint32_t t_sh, run_sh;
-    stage_film(L, tab, &t_sh, &run_sh);
+    stage_film<false>(L, tab, &t_sh, &run_sh);
     int dM = 0, dE = 0, acc = 0;
     phase_tile_bp<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
     const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    finish_block<TX * TY>(L, dM, dE, acc, blin, gridDim.x * gridDim.y * gridDim.z, sigma == 3);
+    finish_block<TX * TY>(L, dM, dE, acc, blin);
 }
 
 template <int TX, int TY, int RY>
@@ -36,14 +38,14 @@ __global__ __launch_bounds__(TX *TY) void k_phase_bp_batch(const BatchEntry *__r
     const uint32_t b = blockIdx.x;
     const BatchEntry &e = ents[find_entry(ents, n_ents, b)];
     const LatDev &L = e.lat;
-    if (!stage_film(L, tab, &t_sh, &run_sh))
+    if (!stage_film<false>(L, tab, &t_sh, &run_sh))
         return;
     const uint32_t bl = b - e.block_begin;
     const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
     const uint32_t by = byz % e.nby, bz = byz / e.nby;
     int dM = 0, dE = 0, acc = 0;
     phase_tile_bp<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
-    finish_block<TX * TY>(L, dM, dE, acc, bl, e.nbx * e.nby * e.nbz, sigma == 3);
+    finish_block<TX * TY>(L, dM, dE, acc, bl);
 }
 
 // Start: spin bit 1 on occupied sites for UP, 0 for DOWN, draw < 2^31 for RANDOM.
@@ -74,12 +76,14 @@ __global__ void k_init_bp(LatDev L, int32_t mode) {
     row[w] = v;
 }
 
-// Recount of M, sum s n, occupied sites and occupied-neighbour pairs.
-__global__ void k_recount_bp(LatDev L, int64_t *out) {
-    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
+// Recount of M, sum s n, occupied sites and occupied-neighbour pairs
+// (grid-stride over all words, one set of atomics per block).
+__global__ __launch_bounds__(256) void k_recount_bp(LatDev L, int64_t *out) {
+    const uint64_t total = (uint64_t)L.Z * L.Y * L.nd;
     int64_t m = 0, sn = 0, no = 0, nb = 0;
-    if (w < L.nd) {
+    for (uint64_t g = blockIdx.x * 256u + threadIdx.x; g < total; g += (uint64_t)gridDim.x * 256u) {
+        const uint32_t w = (uint32_t)(g % L.nd), row = (uint32_t)(g / L.nd);
+        const uint32_t y = row % L.Y, z = row / L.Y;
         const bool left = (((y ^ z) & 1u) == 0);
         const NbBits r = gather_bp(reinterpret_cast<const uint32_t *>(L.spins), L.Y, L.nd, y, z, w, left);
         for (int i = 0; i < 32; ++i) {
@@ -97,16 +101,7 @@ __global__ void k_recount_bp(LatDev L, int64_t *out) {
             nb += 12 - D;
         }
     }
-    m = wave_sum(m);
-    sn = wave_sum(sn);
-    no = wave_sum(no);
-    nb = wave_sum(nb);
-    if ((threadIdx.x & 63) == 0 && (no | m | sn | nb)) {
-        __hip_atomic_fetch_add(&out[0], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&out[1], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&out[2], no, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&out[3], nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    block_add4(out, m, sn, no, nb);
 }
 
 #define ISF_BP_TILINGS(X) X(64, 4, 1) X(64, 4, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) X(16, 16, 2)
@@ -166,8 +161,9 @@ hipError_t launch_init_bp(const LatDev &L, int32_t mode, hipStream_t s) {
 }
 
 hipError_t launch_recount_bp(const LatDev &L, int64_t *out, hipStream_t s) {
-    dim3 g((L.nd + 63) / 64, L.Y, L.Z);
-    hipLaunchKernelGGL(k_recount_bp, g, dim3(64), 0, s, L, out);
+    const uint64_t total = (uint64_t)L.Z * L.Y * L.nd;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(2048, (total + 255) / 256);
+    hipLaunchKernelGGL(k_recount_bp, dim3(blocks), dim3(256), 0, s, L, out);
     return hipGetLastError();
 }
 

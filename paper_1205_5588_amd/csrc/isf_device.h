@@ -2,13 +2,12 @@
 //
 // Per-sweep bookkeeping: blocks add their flips' changes of M (-2 s_old) and
 // E_bond (+2 s_old n) to 64 spread slots with relaxed agent-scope atomics;
-// the last block of the last sublattice of a sweep (found with an atomic
-// counter) folds the slots into M and E, advances the sweep counter, adds the
-// sweep to the step's sums if it is kept, writes the step record when the
-// step ends and stages the next step's threshold table.  All device-state
-// accesses that other blocks of the same launch may race with use agent-scope
-// atomics, so the same code serves one launch per sublattice and the
-// persistent kernel.
+// after the last sublattice of a sweep, one wave per film (a separate small
+// launch, or a block after a grid barrier in the persistent kernel) folds the
+// slots into M and E, advances the sweep counter, adds the sweep to the
+// step's sums if it is kept, writes the step record when the step ends and
+// stages the next step's threshold table.  Device-state accesses use
+// agent-scope atomics so that the same code serves the persistent kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -65,12 +64,25 @@ __device__ __forceinline__ T aadd(T *p, T v) {
 
 // Stage a film's current table and sweep counter into LDS.  Block-wide;
 // ends with a barrier.  Returns false if the film's schedule is finished.
+// kAtomic: the state may have been written earlier in the same launch (the
+// persistent kernel); otherwise a kernel boundary already orders it.
+template <bool kAtomic>
 __device__ __forceinline__ bool stage_film(const LatDev &L, uint32_t *tab, uint32_t *t_sh, uint32_t *run_sh) {
-    if (threadIdx.x < kTableWords)
-        tab[threadIdx.x] = ald(&L.st->cur_table[threadIdx.x]);
-    if (threadIdx.x == 0) {
-        *t_sh = (uint32_t)ald(&L.st->t);
-        *run_sh = ald(&L.st->step) < ald(&L.st->n_steps);
+    if (kAtomic) {
+        if (threadIdx.x < kTableWords)
+            tab[threadIdx.x] = ald(&L.st->cur_table[threadIdx.x]);
+        if (threadIdx.x == 0) {
+            *t_sh = (uint32_t)ald(&L.st->t);
+            *run_sh = ald(&L.st->step) < ald(&L.st->n_steps);
+        }
+    } else {
+        const DevState *st = L.st;
+        if (threadIdx.x < kTableWords)
+            tab[threadIdx.x] = st->cur_table[threadIdx.x];
+        if (threadIdx.x == 0) {
+            *t_sh = (uint32_t)st->t;
+            *run_sh = st->step < st->n_steps;
+        }
     }
     __syncthreads();
     return *run_sh != 0;
@@ -134,7 +146,6 @@ __device__ inline void sweep_end(const LatDev &L) {
             ast(&st->step, step);
             ast(&st->sweep_in_step, sis);
         }
-        ast(&st->done_ctr, 0u);
     }
     next_step = __shfl(next_step, 0, 64);
     if (next_step != 0xFFFFFFFFu && lane < kTableWords)
@@ -142,13 +153,11 @@ __device__ inline void sweep_end(const LatDev &L) {
     __threadfence();
 }
 
-// Block reduction of the per-thread partial sums, slot atomics, and on the
-// last sublattice the sweep end of the last block of the film.
+// Block reduction of the per-thread partial sums and the slot atomics.  No
+// fence here: the sweep end runs in a later launch (or after a grid barrier).
 template <int NT>
-__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat,
-                                             uint32_t blocks_in_lat, bool last_phase) {
+__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat) {
     __shared__ int red[3][NT / 64];
-    __shared__ uint32_t is_last;
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     dM = wave_sum(dM);
     dE = wave_sum(dE);
@@ -167,24 +176,36 @@ __device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, in
             sE += red[1][w];
             sA += red[2][w];
         }
-        Slot *slot = &L.slots[block_in_lat % kSlots];
         if (sA) {
+            Slot *slot = &L.slots[block_in_lat % kSlots];
             aadd(&slot->dM, sM);
             aadd(&slot->dE, sE);
             aadd(&slot->acc, sA);
         }
-        uint32_t last = 0;
-        if (last_phase) {
-            __threadfence();
-            const uint32_t prev = aadd(&L.st->done_ctr, 1u);
-            last = (prev + 1 == blocks_in_lat);
-        }
-        is_last = last;
     }
     __syncthreads();
-    if (is_last && threadIdx.x < 64)
-        sweep_end(L);
+}
+
+// Block-wide sum of four 64-bit values into out[0..3] (256-thread blocks).
+__device__ __forceinline__ void block_add4(int64_t *out, int64_t a, int64_t b, int64_t c, int64_t e) {
+    __shared__ int64_t red[4][4];
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    e = wave_sum(e);
+    if (lane == 0) {
+        red[0][wid] = a;
+        red[1][wid] = b;
+        red[2][wid] = c;
+        red[3][wid] = e;
+    }
     __syncthreads();
+    if (threadIdx.x < 4) {
+        const int64_t v = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (v)
+            aadd(&out[threadIdx.x], v);
+    }
 }
 
 // Linear block index -> film entry of a batched launch table (binary search).

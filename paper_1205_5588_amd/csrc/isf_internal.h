@@ -41,7 +41,7 @@ struct alignas(256) DevState {
     int64_t sum_absM;
     int64_t sum_E;
     int64_t accepted;
-    uint32_t done_ctr;      // blocks finished in the current last-phase launch
+    uint32_t reserved0;
     uint32_t n_steps;       // length of the loaded schedule
     int64_t n_occ;
     int64_t n_bonds;

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "isf_tiles.h"
 
 namespace isf {
@@ -32,11 +34,11 @@ template <int TX, int TY, int RY>
 __global__ __launch_bounds__(TX *TY) void k_phase_i8(LatDev L, uint32_t sigma) {
     __shared__ uint32_t tab[kTableWords];
     __shared__ uint32_t t_sh, run_sh;
-    stage_film(L, tab, &t_sh, &run_sh);
+    stage_film<false>(L, tab, &t_sh, &run_sh);
     int dM = 0, dE = 0, acc = 0;
     phase_tile_i8<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
     const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    finish_block<TX * TY>(L, dM, dE, acc, blin, gridDim.x * gridDim.y * gridDim.z, sigma == 3);
+    finish_block<TX * TY>(L, dM, dE, acc, blin);
 }
 
 // Batched: one launch covers the same sublattice of many films.  Block b
@@ -49,14 +51,25 @@ __global__ __launch_bounds__(TX *TY) void k_phase_i8_batch(const BatchEntry *__r
     const uint32_t b = blockIdx.x;
     const BatchEntry &e = ents[find_entry(ents, n_ents, b)];
     const LatDev &L = e.lat;
-    if (!stage_film(L, tab, &t_sh, &run_sh))
+    if (!stage_film<false>(L, tab, &t_sh, &run_sh))
         return;  // this film's schedule is finished; uniform across the block
     const uint32_t bl = b - e.block_begin;
     const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
     const uint32_t by = byz % e.nby, bz = byz / e.nby;
     int dM = 0, dE = 0, acc = 0;
     phase_tile_i8<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
-    finish_block<TX * TY>(L, dM, dE, acc, bl, e.nbx * e.nby * e.nbz, sigma == 3);
+    finish_block<TX * TY>(L, dM, dE, acc, bl);
+}
+
+// --------------------------------------------------------------------------
+// Sweep end of one film (one wave), or of every running film of a batch (one
+// wave per film), launched after the last sublattice of each sweep.
+__global__ __launch_bounds__(64) void k_sweep_end(LatDev L) { sweep_end(L); }
+
+__global__ __launch_bounds__(64) void k_sweep_end_batch(const BatchEntry *__restrict__ ents, uint32_t n_ents) {
+    const LatDev &L = ents[blockIdx.x].lat;
+    if (L.st->step < L.st->n_steps)
+        sweep_end(L);
 }
 
 // --------------------------------------------------------------------------
@@ -96,12 +109,14 @@ __global__ void k_init_i8(LatDev L, int32_t mode) {
 }
 
 // Full recount of M, sum_i s_i n_i, occupied sites and occupied-neighbour
-// pairs, from the spins alone.  out[4] must be zero on entry.
-__global__ void k_recount_i8(LatDev L, int64_t *out) {
-    const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
-    int m = 0, sn = 0, no = 0, nb = 0;
-    if (d < L.nd) {
+// pairs, from the spins alone.  Grid-stride over all dwords; one set of
+// atomics per block.  out[4] must be zero on entry.
+__global__ __launch_bounds__(256) void k_recount_i8(LatDev L, int64_t *out) {
+    const uint64_t total = (uint64_t)L.Z * L.Y * L.nd;
+    int64_t m = 0, sn = 0, no = 0, nb = 0;
+    for (uint64_t g = blockIdx.x * 256u + threadIdx.x; g < total; g += (uint64_t)gridDim.x * 256u) {
+        const uint32_t d = (uint32_t)(g % L.nd), row = (uint32_t)(g / L.nd);
+        const uint32_t y = row % L.Y, z = row / L.Y;
         const bool left = (((y ^ z) & 1u) == 0);
         const Nb r = gather_i8<true>(reinterpret_cast<const uint32_t *>(L.spins), L.Y, L.nd, y, z, d, left);
 #pragma unroll
@@ -117,16 +132,7 @@ __global__ void k_recount_i8(LatDev L, int64_t *out) {
             nb += (int)((r.occsum >> (8 * i)) & 0xFFu);
         }
     }
-    m = wave_sum(m);
-    sn = wave_sum(sn);
-    no = wave_sum(no);
-    nb = wave_sum(nb);
-    if ((threadIdx.x & 63) == 0 && (no | m | sn | nb)) {
-        aadd(&out[0], (int64_t)m);
-        aadd(&out[1], (int64_t)sn);
-        aadd(&out[2], (int64_t)no);
-        aadd(&out[3], (int64_t)nb);
-    }
+    block_add4(out, m, sn, no, nb);
 }
 
 // --------------------------------------------------------------------------
@@ -177,6 +183,16 @@ hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, ui
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_sweep_end(const LatDev &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(64), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_end_batch, dim3(n_ents), dim3(64), 0, s, ents_dev, n_ents);
+    return hipGetLastError();
+}
+
 bool tiling_supported(const Tiling &tl) {
 #define X(a, b, c) \
     if (tl.tx == a && tl.ty == b && tl.ry == c) return true;
@@ -192,8 +208,9 @@ hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s) {
 }
 
 hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s) {
-    dim3 g((L.nd + 255) / 256, L.Y, L.Z);
-    hipLaunchKernelGGL(k_recount_i8, g, dim3(256), 0, s, L, out);
+    const uint64_t total = (uint64_t)L.Z * L.Y * L.nd;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(2048, (total + 255) / 256);
+    hipLaunchKernelGGL(k_recount_i8, dim3(blocks), dim3(256), 0, s, L, out);
     return hipGetLastError();
 }
 

@@ -6,8 +6,9 @@
 // tiles; every resident block takes tiles from that list, then all blocks
 // meet at a grid-wide barrier before the next sublattice (no two neighbours
 // share a sublattice, but a sublattice reads what the previous one wrote).
-// Per-film bookkeeping (sweep counter, step sums, records, next table) is the
-// same last-block logic as in the one-launch-per-phase kernels.
+// Per-film bookkeeping (sweep counter, step sums, records, next table) runs
+// after the last sublattice of each sweep, one wave per film, followed by one
+// more barrier.
 //
 // Tile -> block mapping is XCD-aware: MI355X dispatches consecutive blocks
 // round-robin over its 8 XCDs, each with its own L2, so block b works on the
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(TX *TY) void k_persistent(const BatchEntry *__restr
                 const BatchEntry &e = ents[find_entry(ents, n_ents, tile)];
                 const LatDev &L = e.lat;
                 __syncthreads();  // previous tile's readers of tab are done
-                if (!stage_film(L, tab, &t_sh, &run_sh))
+                if (!stage_film<true>(L, tab, &t_sh, &run_sh))
                     continue;
                 const uint32_t bl = tile - e.block_begin;
                 const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
@@ -84,11 +85,19 @@ __global__ __launch_bounds__(TX *TY) void k_persistent(const BatchEntry *__restr
                     phase_tile_i8<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
                 else
                     phase_tile_bp<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
-                finish_block<TX * TY>(L, dM, dE, acc, bl, e.nbx * e.nby * e.nbz, sigma == 3);
+                finish_block<TX * TY>(L, dM, dE, acc, bl);
             }
             if (!grid_barrier(bar, G, gen))
                 return;
         }
+        // sweep end: one wave per running film, then every block sees the new state
+        for (uint32_t f = blockIdx.x; f < n_ents; f += G) {
+            const LatDev &L = ents[f].lat;
+            if (threadIdx.x < 64 && ald(&L.st->step) < ald(&L.st->n_steps))
+                sweep_end(L);
+        }
+        if (!grid_barrier(bar, G, gen))
+            return;
     }
 }
 

@@ -59,6 +59,16 @@ __device__ __forceinline__ Nb gather_i8(const uint32_t *P, uint32_t Y, uint32_t 
 
 // --------------------------------------------------------------------------
 // One tile of one sublattice phase (INT8 format).
+//
+// Addressing: the block's plane z and its neighbours z-1, z+1 are uniform, so
+// their base addresses live in scalar registers and every load is a 32-bit
+// byte offset from them.  All rows of a thread are loaded before any is
+// computed, so their memory latency overlaps.  Rows past the film end are
+// clamped to a valid row and discarded.
+__device__ __forceinline__ uint32_t ldw(const char *base, uint32_t off) {
+    return *reinterpret_cast<const uint32_t *>(base + off);
+}
+
 template <int TX, int TY, int RY>
 __device__ __forceinline__ void phase_tile_i8(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
                                               const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
@@ -69,41 +79,69 @@ __device__ __forceinline__ void phase_tile_i8(const LatDev &L, uint32_t sigma, u
     if (z >= L.Z || d >= L.nd)
         return;
     const uint32_t Y = L.Y, nd = L.nd, half = Y >> 1;
-    uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
+    const uint32_t rowb = nd * 4u;           // bytes per row
+    const size_t planeb = (size_t)Y * rowb;  // bytes per plane
+    char *c1p = reinterpret_cast<char *>(L.spins) + (size_t)(z + 1) * planeb;  // plane z
+    const char *c0p = c1p - planeb;                                            // plane z-1
+    const char *c2p = c1p + planeb;                                            // plane z+1
     const bool left = ((py ^ pz) == 0);
+    const uint32_t db = d * 4u;
+    const uint32_t ddb = (left ? (d == 0 ? nd - 1 : d - 1) : (d + 1 == nd ? 0 : d + 1)) * 4u;
+
+    uint32_t A[RY], S[RY], off[RY];
+    bool ok[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const uint32_t yi = (by * RY + r) * TY + ty;
-        if (yi >= half)
-            break;
-        const uint32_t y = 2 * yi + py;
-        const Nb nb = gather_i8<false>(P, Y, nd, y, z, d, left);
-        const uint32_t A = nb.self;
-        const uint32_t occ = ~A & 0x01010101u;  // 1 in each byte of an occupied site
-        if (!occ)
+        ok[r] = yi < half;
+        const uint32_t y = ok[r] ? 2 * yi + py : py;
+        const uint32_t ym = y == 0 ? Y - 1 : y - 1;
+        const uint32_t yp = y + 1 == Y ? 0 : y + 1;
+        // y < 2^16 and rowb < 2^24: 24-bit multiplies are exact
+        const uint32_t oy = __umul24(y, rowb), om = __umul24(ym, rowb), op = __umul24(yp, rowb);
+        off[r] = oy + db;
+        const uint32_t a1 = ldw(c1p, om + db), a1o = ldw(c1p, om + ddb);
+        const uint32_t a2 = ldw(c1p, op + db), a2o = ldw(c1p, op + ddb);
+        const uint32_t b1 = ldw(c0p, oy + db), b1o = ldw(c0p, oy + ddb);
+        const uint32_t b2 = ldw(c2p, oy + db), b2o = ldw(c2p, oy + ddb);
+        const uint32_t e1 = ldw(c0p, om + db), e2 = ldw(c0p, op + db);
+        const uint32_t e3 = ldw(c2p, om + db), e4 = ldw(c2p, op + db);
+        A[r] = ldw(c1p, oy + db);
+        S[r] = (a1 + a2) + (b1 + b2) + ((shifted(left, a1, a1o) + shifted(left, a2, a2o)) +
+                                        (shifted(left, b1, b1o) + shifted(left, b2, b2o))) +
+               ((e1 + e2) + (e3 + e4));
+    }
+    const uint32_t cz = z * Y * nd;  // Philox counter word 0 of row (z, 0), dword 0
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const uint32_t a = A[r];
+        const uint32_t occ = ~a & 0x01010101u;  // 1 in each byte of an occupied site
+        if (!ok[r] || !occ)
             continue;
         uint32_t u[4];
-        philox((z * Y + y) * nd + d, t, L.replica, sigma, L.key0, L.key1, u);
+        philox(cz + off[r] / 4u, t, L.replica, sigma, L.key0, L.key1, u);
+        // table index per byte: n + 12 + 25 [s = +1]  (<= 49)
+        const uint32_t key = S[r] + ((a >> 1) & 0x01010101u) * 25u;
         uint32_t F = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint32_t b = (A >> (8 * i)) & 0xFFu;
-            const uint32_t s = (nb.sum >> (8 * i)) & 0xFFu;
-            if (b != 1u) {
-                const uint32_t thr = tab[s + (b >> 1) * 25u];
-                if (thr == kSentinel || u[i] < thr) {
-                    F |= 2u << (8 * i);
-                    dM += 2 - 2 * (int)b;
-                    dE += 2 * ((int)b - 1) * ((int)s - 12);
-                    acc += 1;
-                }
-            }
+            const uint32_t thr = tab[(key >> (8 * i)) & 0xFFu];
+            F |= ((u[i] < thr) | (thr == kSentinel)) ? (2u << (8 * i)) : 0u;
         }
-        if (F)
-            P[((size_t)(z + 1) * Y + y) * nd + d] = A ^ F;
+        F &= occ << 1;  // vacancies never flip
+        if (!F)
+            continue;
+        // observables: up spins flipped (byte 2 in a & F) and down spins flipped
+        const uint32_t fu = F & a, fd = F ^ fu;
+        const int cu = __popc(fu), cd = __popc(fd);
+        const uint32_t su = __builtin_amdgcn_sad_u8(S[r] & ((fu >> 1) * 0xFFu), 0u, 0u);
+        const uint32_t sd = __builtin_amdgcn_sad_u8(S[r] & ((fd >> 1) * 0xFFu), 0u, 0u);
+        dM += 2 * (cd - cu);
+        dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
+        acc += cu + cd;
+        *reinterpret_cast<uint32_t *>(c1p + off[r]) = a ^ F;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // BITPACK format (spin bit + occupancy bit per site)

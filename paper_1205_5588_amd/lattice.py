@@ -81,7 +81,9 @@ class Lattice:
         self.aux_buf = aux_buf if aux_buf is not None else torch.empty(ab, dtype=torch.uint8, device=self.device)
         if self.spin_buf.numel() < sb or self.aux_buf.numel() < ab:
             raise ValueError("lattice buffers too small")
-        torch.cuda.synchronize(self.device)
+        # the buffers were allocated on torch's current stream; order the library's stream after it
+        # (no device-wide synchronisation: other films may be running)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(_lib.load().isf_lattice_create(ctypes.byref(self._desc), h.ctypes.data, int(init),

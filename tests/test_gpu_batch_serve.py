@@ -1,0 +1,128 @@
+"""GPU: the batched workload (uneven films x temperatures in one launch per
+sublattice or one persistent launch) and the serving loop (continuous
+batching) give every replica / request exactly the trajectory it has alone,
+and sampled replicas match the CPU oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def isf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1205_5588_amd import lattice
+
+    return lattice
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_config_batched_sampled(isf, mode):
+    """All 256 replicas of the batched workload on a prefix of the ramp: batched ==
+    alone for a spread of replicas, and the smallest films == oracle over the
+    same prefix."""
+    import torch
+
+    from isf_workloads import batched_films
+
+    reps, seed, hnums, spst = batched_films()
+    n_steps = 3
+    sched = lambda r: [(r.T, h, spst, 0) for h in hnums[:n_steps]]
+    stream = torch.cuda.Stream()
+    _say("batched config, mode", mode)
+    lats = [isf.Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
+    b = isf.Batch(len(lats), stream=stream)
+    recs = b.run(lats, [sched(r) for r in reps], mode=mode)
+    # batched == alone for every 17th replica
+    for i in range(0, len(reps), 17):
+        r = reps[i]
+        alone = isf.Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0)
+        np.testing.assert_array_equal(alone.run_schedule(sched(r)), recs[i], err_msg="replica %d" % r.replica)
+        np.testing.assert_array_equal(alone.spins(), lats[i].spins())
+    # oracle on the replicas of the smallest film
+    small = min(range(16), key=lambda f: reps[16 * f].X * reps[16 * f].Y * reps[16 * f].Z)
+    for j in (0, 7, 15):
+        r = reps[16 * small + j]
+        o = cpu.Film(r.heights(), r.Z, seed, r.replica, init=0)
+        np.testing.assert_array_equal(np.array([o.run(*s).as_tuple() for s in sched(r)]), recs[16 * small + j])
+
+
+def test_config_batched_full_ramp_small_replica(isf):
+    """One replica of the smallest batched film over its whole ramp (201 steps x 20
+    sweeps) inside a batch of 16 replicas: equal to the oracle."""
+    import torch
+
+    from isf_workloads import batched_films
+
+    reps, seed, hnums, spst = batched_films()
+    small = min(range(16), key=lambda f: reps[16 * f].X * reps[16 * f].Y * reps[16 * f].Z)
+    group = reps[16 * small:16 * small + 16]
+    stream = torch.cuda.Stream()
+    _say("batched full ramp, film", small)
+    lats = [isf.Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in group]
+    b = isf.Batch(len(lats), stream=stream)
+    recs = b.run(lats, [[(r.T, h, spst, 0) for h in hnums] for r in group], mode=1)
+    r = group[5]
+    o = cpu.Film(r.heights(), r.Z, seed, r.replica, init=0)
+    np.testing.assert_array_equal(cpu.hysteresis(o, r.T, hnums, spst), recs[5])
+    np.testing.assert_array_equal(o.spins(), lats[5].spins())
+
+
+def _small_requests(n=10):
+    from isf_workloads import ServeRequest, ramp_hnum
+
+    rng = np.random.default_rng(9)
+    reqs = []
+    t = 0.0
+    for i in range(n):
+        t += float(rng.exponential(0.01))
+        side = int(rng.choice([64, 96, 128, 200]))
+        Z = int(rng.integers(1, 5))
+        q = ServeRequest(rid=i, arrival=t, seed=int(rng.integers(1, 2**60)), X=side, Y=side, Z=Z,
+                         sigma=float(rng.uniform(2, 16)), T=float(rng.uniform(1, 9)),
+                         kind="hysteresis" if i % 2 == 0 else "tscan")
+        if q.kind == "hysteresis":
+            q.h_nums = ramp_hnum(100, 20)
+            q.sweeps_per_step = int(rng.integers(3, 9))
+        else:
+            q.temps = [float(v) for v in np.linspace(10.0, q.T, 4)]
+            q.sweeps_per_T = 12
+            q.discard_per_T = 4
+        reqs.append(q)
+    return reqs
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_serving_alone_equals_in_mix(isf, mode):
+    from paper_1205_5588_amd.serve import GpuExecutor, Job, Server, request_schedule
+
+    reqs = _small_requests()
+    jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q), n_sweeps=q.n_sweeps, payload=q)
+            for q in reqs]
+    _say("serving mode", mode)
+    srv = Server(GpuExecutor(max_slots=4, mode=mode), budget_bytes=10**9, max_slots=4, target_chunk_s=0.001,
+                 rate_estimate=1e10, max_chunk=16)
+    stats = srv.run(jobs)
+    assert len(stats.results) == len(reqs) and stats.max_active <= 4
+    for q, res in zip(reqs, stats.results):
+        alone = isf.Lattice(q.heights(), q.Z, q.seed, replica=0, init=q.init)
+        np.testing.assert_array_equal(alone.run_schedule(request_schedule(q)), res.records,
+                                      err_msg="request %d" % q.rid)
+    for q, res in list(zip(reqs, stats.results))[:3]:
+        o = cpu.Film(q.heights(), q.Z, q.seed, 0, init=q.init)
+        np.testing.assert_array_equal(np.array([o.run(*s).as_tuple() for s in request_schedule(q)]), res.records)
+    s = stats.summary()
+    assert s["p99_s"] >= s["p50_s"] > 0
