@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=512)
     ap.add_argument("--serve-mode", type=int, default=0)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -274,6 +276,15 @@ def main():
     if not args.no_cpu:
         cpu_base = cpu_baseline(cfg, h)
         log("cpu baseline:", cpu_base)
+
+    if args.copy_mib:
+        n = args.copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d bytes" % n)
 
     Nc = cfg.X * cfg.Y * cfg.Z // 2
     line = {

@@ -180,6 +180,7 @@ int32_t launch_end(const isf_lattice *lat) {
     return ISF_OK;
 }
 
+// One sweep = four sublattice launches and the one-wave sweep-end launch.
 int32_t enqueue_sweeps_plain(const isf_lattice *lat, uint64_t n) {
     for (uint64_t i = 0; i < n; ++i) {
         for (uint32_t s = 0; s < 4; ++s) {
@@ -272,9 +273,7 @@ void build_layout(const isf_desc &d, const uint8_t *h, std::vector<uint8_t> &buf
 }
 
 int32_t recount(isf_lattice *lat, int64_t out[4]) {
-    // scratch: the record area's first 32 bytes are free outside a schedule run;
-    // use a dedicated spot after the slots instead to keep records intact.
-    int64_t *dev = reinterpret_cast<int64_t *>(lat->aux_dev + lat->aux.off_slots) + 3;  // slot 0 pad words
+    int64_t *dev = reinterpret_cast<int64_t *>(lat->aux_dev + offsetof(DevState, recount));
     HIP_TRY(hipMemsetAsync(dev, 0, 4 * sizeof(int64_t), lat->stream));
     hipError_t e = lat->d.format == ISF_FORMAT_INT8 ? launch_recount_i8(lat->L, dev, lat->stream)
                                                     : launch_recount_bp(lat->L, dev, lat->stream);
@@ -491,7 +490,7 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
     struct {
         uint32_t step, sweep_in_step;
         int64_t sum_M, sum_absM, sum_E, accepted;
-        uint32_t done_ctr, n_steps;
+        uint32_t reserved0, n_steps;
     } mid = {0, 0, 0, 0, 0, 0, 0, n};
     static_assert(offsetof(DevState, n_steps) + 4 - offsetof(DevState, step) == sizeof(mid), "state layout");
     if (n) {

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #include "isf_internal.h"
 
@@ -26,8 +27,9 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input XOR in one gfx950 instruction (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -88,18 +90,34 @@ __device__ __forceinline__ bool stage_film(const LatDev &L, uint32_t *tab, uint3
     return *run_sh != 0;
 }
 
-// Sweep end, run by the 64 lanes of one wave.
+// Sweep end, run by the 64 lanes of one wave.  kAtomic: agent-scope atomics
+// for state written earlier in the same launch (persistent kernel); plain
+// accesses when a kernel boundary orders everything (separate launch).
+template <bool kAtomic, typename T>
+__device__ __forceinline__ T sld(const T *p) {
+    if (kAtomic)
+        return ald(p);
+    return *p;
+}
+template <bool kAtomic, typename T>
+__device__ __forceinline__ void sst(T *p, T v) {
+    if (kAtomic)
+        ast(p, v);
+    else
+        *p = v;
+}
+
+template <bool kAtomic>
 __device__ inline void sweep_end(const LatDev &L) {
     const uint32_t lane = threadIdx.x & 63;
-    __threadfence();
     int64_t dM = 0, dE = 0, acc = 0;
     for (uint32_t s = lane; s < kSlots; s += 64) {
-        dM += ald(&L.slots[s].dM);
-        dE += ald(&L.slots[s].dE);
-        acc += ald(&L.slots[s].acc);
-        ast(&L.slots[s].dM, (int64_t)0);
-        ast(&L.slots[s].dE, (int64_t)0);
-        ast(&L.slots[s].acc, (int64_t)0);
+        dM += sld<kAtomic>(&L.slots[s].dM);
+        dE += sld<kAtomic>(&L.slots[s].dE);
+        acc += sld<kAtomic>(&L.slots[s].acc);
+        sst<kAtomic>(&L.slots[s].dM, (int64_t)0);
+        sst<kAtomic>(&L.slots[s].dE, (int64_t)0);
+        sst<kAtomic>(&L.slots[s].acc, (int64_t)0);
     }
     dM = wave_sum(dM);
     dE = wave_sum(dE);
@@ -107,17 +125,19 @@ __device__ inline void sweep_end(const LatDev &L) {
     DevState *st = L.st;
     uint32_t next_step = 0xFFFFFFFFu;
     if (lane == 0) {
-        const int64_t M = ald(&st->M) + dM;
-        const int64_t E = ald(&st->E) + dE;
-        ast(&st->M, M);
-        ast(&st->E, E);
-        ast(&st->t, ald(&st->t) + 1);
-        uint32_t step = ald(&st->step);
-        uint32_t sis = ald(&st->sweep_in_step);
-        if (step < ald(&st->n_steps)) {
-            const uint32_t n_sweeps = ald(&L.steps[step].n_sweeps);
-            const uint32_t n_discard = ald(&L.steps[step].n_discard);
-            int64_t sM = ald(&st->sum_M), sA = ald(&st->sum_absM), sE = ald(&st->sum_E), sC = ald(&st->accepted);
+        const int64_t M = sld<kAtomic>(&st->M) + dM;
+        const int64_t E = sld<kAtomic>(&st->E) + dE;
+        sst<kAtomic>(&st->M, M);
+        sst<kAtomic>(&st->E, E);
+        sst<kAtomic>(&st->t, sld<kAtomic>(&st->t) + 1);
+        uint32_t step = sld<kAtomic>(&st->step);
+        uint32_t sis = sld<kAtomic>(&st->sweep_in_step);
+        const uint32_t n_steps = sld<kAtomic>(&st->n_steps);
+        if (step < n_steps) {
+            const uint32_t n_sweeps = sld<kAtomic>(&L.steps[step].n_sweeps);
+            const uint32_t n_discard = sld<kAtomic>(&L.steps[step].n_discard);
+            int64_t sM = sld<kAtomic>(&st->sum_M), sA = sld<kAtomic>(&st->sum_absM);
+            int64_t sE = sld<kAtomic>(&st->sum_E), sC = sld<kAtomic>(&st->accepted);
             if (sis >= n_discard) {
                 sM += M;
                 sA += M < 0 ? -M : M;
@@ -127,34 +147,38 @@ __device__ inline void sweep_end(const LatDev &L) {
             ++sis;
             if (sis >= n_sweeps) {
                 isf_record *rec = &L.records[step];
-                ast(&rec->M, M);
-                ast(&rec->E, E);
-                ast(&rec->sum_M, sM);
-                ast(&rec->sum_absM, sA);
-                ast(&rec->sum_E, sE);
-                ast(&rec->accepted, sC);
+                sst<kAtomic>(&rec->M, M);
+                sst<kAtomic>(&rec->E, E);
+                sst<kAtomic>(&rec->sum_M, sM);
+                sst<kAtomic>(&rec->sum_absM, sA);
+                sst<kAtomic>(&rec->sum_E, sE);
+                sst<kAtomic>(&rec->accepted, sC);
                 sM = sA = sE = sC = 0;
                 ++step;
                 sis = 0;
-                if (step < ald(&st->n_steps))
+                if (step < n_steps)
                     next_step = step;
             }
-            ast(&st->sum_M, sM);
-            ast(&st->sum_absM, sA);
-            ast(&st->sum_E, sE);
-            ast(&st->accepted, sC);
-            ast(&st->step, step);
-            ast(&st->sweep_in_step, sis);
+            sst<kAtomic>(&st->sum_M, sM);
+            sst<kAtomic>(&st->sum_absM, sA);
+            sst<kAtomic>(&st->sum_E, sE);
+            sst<kAtomic>(&st->accepted, sC);
+            sst<kAtomic>(&st->step, step);
+            sst<kAtomic>(&st->sweep_in_step, sis);
         }
     }
     next_step = __shfl(next_step, 0, 64);
     if (next_step != 0xFFFFFFFFu && lane < kTableWords)
-        ast(&st->cur_table[lane], ald(&L.tables[(size_t)next_step * kTableWords + lane]));
-    __threadfence();
+        sst<kAtomic>(&st->cur_table[lane], sld<kAtomic>(&L.tables[(size_t)next_step * kTableWords + lane]));
 }
 
 // Block reduction of the per-thread partial sums and the slot atomics.  No
-// fence here: the sweep end runs in a later launch (or after a grid barrier).
+// fence and no returning atomics here: the sweep end runs in a later launch
+// (or after a grid barrier).  Measured on MI355X, folding the sweep end into
+// the last sublattice launch costs more than the extra launch, whether the
+// last block is found behind a device-scope fence per block (an L2 write-back
+// each) or through returning atomics (a memory round trip before every block
+// can retire).
 template <int NT>
 __device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat) {
     __shared__ int red[3][NT / 64];

@@ -45,6 +45,7 @@ struct alignas(256) DevState {
     uint32_t n_steps;       // length of the loaded schedule
     int64_t n_occ;
     int64_t n_bonds;
+    int64_t recount[4];     // scratch of the full recount (M, sum s n, sites, occupied pairs)
     uint32_t cur_table[kTableWords];  // thresholds of the current step
 };
 

@@ -32,11 +32,8 @@ namespace isf {
 
 template <int TX, int TY, int RY>
 __global__ __launch_bounds__(TX *TY) void k_phase_i8(LatDev L, uint32_t sigma) {
-    __shared__ uint32_t tab[kTableWords];
-    __shared__ uint32_t t_sh, run_sh;
-    stage_film<false>(L, tab, &t_sh, &run_sh);
     int dM = 0, dE = 0, acc = 0;
-    phase_tile_i8<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
+    phase_block_i8<TX, TY, RY, false>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, dM, dE, acc);
     const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     finish_block<TX * TY>(L, dM, dE, acc, blin);
 }
@@ -46,30 +43,27 @@ __global__ __launch_bounds__(TX *TY) void k_phase_i8(LatDev L, uint32_t sigma) {
 template <int TX, int TY, int RY>
 __global__ __launch_bounds__(TX *TY) void k_phase_i8_batch(const BatchEntry *__restrict__ ents, uint32_t n_ents,
                                                            uint32_t sigma) {
-    __shared__ uint32_t tab[kTableWords];
-    __shared__ uint32_t t_sh, run_sh;
     const uint32_t b = blockIdx.x;
     const BatchEntry &e = ents[find_entry(ents, n_ents, b)];
     const LatDev &L = e.lat;
-    if (!stage_film<false>(L, tab, &t_sh, &run_sh))
-        return;  // this film's schedule is finished; uniform across the block
     const uint32_t bl = b - e.block_begin;
     const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
     const uint32_t by = byz % e.nby, bz = byz / e.nby;
     int dM = 0, dE = 0, acc = 0;
-    phase_tile_i8<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
+    if (!phase_block_i8<TX, TY, RY, false>(L, sigma, bx, by, bz, dM, dE, acc))
+        return;  // finished film: uniform over the block, and no other block of it counts either
     finish_block<TX * TY>(L, dM, dE, acc, bl);
 }
 
 // --------------------------------------------------------------------------
 // Sweep end of one film (one wave), or of every running film of a batch (one
 // wave per film), launched after the last sublattice of each sweep.
-__global__ __launch_bounds__(64) void k_sweep_end(LatDev L) { sweep_end(L); }
+__global__ __launch_bounds__(64) void k_sweep_end(LatDev L) { sweep_end<false>(L); }
 
 __global__ __launch_bounds__(64) void k_sweep_end_batch(const BatchEntry *__restrict__ ents, uint32_t n_ents) {
     const LatDev &L = ents[blockIdx.x].lat;
     if (L.st->step < L.st->n_steps)
-        sweep_end(L);
+        sweep_end<false>(L);
 }
 
 // --------------------------------------------------------------------------

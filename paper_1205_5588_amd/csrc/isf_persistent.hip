@@ -74,17 +74,18 @@ __global__ __launch_bounds__(TX *TY) void k_persistent(const BatchEntry *__restr
             for (uint32_t tile = t_lo + rank; tile < t_hi; tile += per_xcd) {
                 const BatchEntry &e = ents[find_entry(ents, n_ents, tile)];
                 const LatDev &L = e.lat;
-                __syncthreads();  // previous tile's readers of tab are done
-                if (!stage_film<true>(L, tab, &t_sh, &run_sh))
-                    continue;
+                __syncthreads();  // previous tile's readers of LDS are done
                 const uint32_t bl = tile - e.block_begin;
                 const uint32_t bx = bl % e.nbx, byz = bl / e.nbx;
                 const uint32_t by = byz % e.nby, bz = byz / e.nby;
                 int dM = 0, dE = 0, acc = 0;
-                if (FORMAT == ISF_FORMAT_INT8)
-                    phase_tile_i8<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
-                else
+                if (FORMAT == ISF_FORMAT_INT8) {
+                    phase_block_i8<TX, TY, RY, true>(L, sigma, bx, by, bz, dM, dE, acc);
+                } else {
+                    if (!stage_film<true>(L, tab, &t_sh, &run_sh))
+                        continue;
                     phase_tile_bp<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
+                }
                 finish_block<TX * TY>(L, dM, dE, acc, bl);
             }
             if (!grid_barrier(bar, G, gen))
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(TX *TY) void k_persistent(const BatchEntry *__restr
         for (uint32_t f = blockIdx.x; f < n_ents; f += G) {
             const LatDev &L = ents[f].lat;
             if (threadIdx.x < 64 && ald(&L.st->step) < ald(&L.st->n_steps))
-                sweep_end(L);
+                sweep_end<true>(L);
         }
         if (!grid_barrier(bar, G, gen))
             return;
@@ -122,7 +123,11 @@ static hipError_t launch_one(const BatchEntry *ents, uint32_t n_ents, uint32_t t
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess)
             return e;
-        max_blocks = per_cu * cus;
+        // Half the occupancy limit: a grid barrier needs every block resident, and a
+        // grid at the theoretical maximum leaves no slack for anything else the
+        // device keeps on its compute units.  Blocks loop over tiles, so fewer
+        // blocks still cover all the work.
+        max_blocks = std::max(1, per_cu / 2) * cus;
     }
     uint32_t grid = std::min<uint32_t>((uint32_t)max_blocks, total);
     if (grid == 0)

@@ -69,78 +69,167 @@ __device__ __forceinline__ uint32_t ldw(const char *base, uint32_t off) {
     return *reinterpret_cast<const uint32_t *>(base + off);
 }
 
-template <int TX, int TY, int RY>
-__device__ __forceinline__ void phase_tile_i8(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
-                                              const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
+// One block of one sublattice phase (INT8), with the occupied dwords
+// compacted.  About half of all dwords hold only vacancies, but nearly every
+// 64-dword wave span holds some occupied site, so skipping has to happen
+// inside the block:
+//   1. every thread issues the loads of its RY slots (self + 12 neighbour
+//      dwords each) and of the film state (table, sweep counter), then forms
+//      the biased neighbour sums;
+//   2. slots with an occupied site are compacted into LDS in row-major order
+//      (wave ballot + mbcnt, block prefix over the (row, wave) counts);
+//   3. the Philox draws, acceptance, flips and observables run only on the
+//      compacted slots, 256 at a time.
+// kAtomic selects agent-scope atomic loads of the film state (needed when the
+// state may change inside the same launch, i.e. in the persistent kernel).
+// Returns false (uniformly over the block) if the film's schedule is finished.
+template <int TX, int TY, int RY, bool kAtomic>
+__device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
+                                               int &dM, int &dE, int &acc) {
+    constexpr int NT = TX * TY;
+    constexpr int NS = NT * RY;
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh, run_sh;
+    __shared__ uint32_t lA[NS], lS[NS];
+    __shared__ uint16_t lslot[NS];
+    __shared__ uint32_t wcnt[RY * (NT / 64) + 1];
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    // film state: issued first, consumed after the barrier
+    uint32_t tabv = 0, tv = 0, runv = 0;
+    if (kAtomic) {
+        if (tid < kTableWords)
+            tabv = ald(&L.st->cur_table[tid]);
+        if (tid == 0) {
+            tv = (uint32_t)ald(&L.st->t);
+            runv = ald(&L.st->step) < ald(&L.st->n_steps);
+        }
+    } else {
+        if (tid < kTableWords)
+            tabv = L.st->cur_table[tid];
+        if (tid == 0) {
+            tv = (uint32_t)L.st->t;
+            runv = L.st->step < L.st->n_steps;
+        }
+    }
+
     const uint32_t py = sigma & 1u, pz = sigma >> 1;
     const uint32_t z = 2 * bz + pz;
-    const uint32_t tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const uint32_t d = bx * TX + tx;
-    if (z >= L.Z || d >= L.nd)
-        return;
+    const bool zok = z < L.Z;  // uniform over the block
+    const uint32_t tx = tid % TX, ty = tid / TX;
     const uint32_t Y = L.Y, nd = L.nd, half = Y >> 1;
-    const uint32_t rowb = nd * 4u;           // bytes per row
-    const size_t planeb = (size_t)Y * rowb;  // bytes per plane
-    char *c1p = reinterpret_cast<char *>(L.spins) + (size_t)(z + 1) * planeb;  // plane z
-    const char *c0p = c1p - planeb;                                            // plane z-1
-    const char *c2p = c1p + planeb;                                            // plane z+1
+    const uint32_t d_raw = bx * TX + tx;
+    const bool dok = d_raw < nd;
+    const uint32_t d = dok ? d_raw : nd - 1;
+    const uint32_t rowb = nd * 4u;
+    const size_t planeb = (size_t)Y * rowb;
+    char *c1p = reinterpret_cast<char *>(L.spins) + (size_t)(zok ? z + 1 : 1) * planeb;
+    const char *c0p = c1p - planeb;
+    const char *c2p = c1p + planeb;
     const bool left = ((py ^ pz) == 0);
     const uint32_t db = d * 4u;
     const uint32_t ddb = (left ? (d == 0 ? nd - 1 : d - 1) : (d + 1 == nd ? 0 : d + 1)) * 4u;
 
-    uint32_t A[RY], S[RY], off[RY];
-    bool ok[RY];
+    uint32_t A[RY], S[RY];
+    bool need[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const uint32_t yi = (by * RY + r) * TY + ty;
-        ok[r] = yi < half;
-        const uint32_t y = ok[r] ? 2 * yi + py : py;
+        const bool ok = zok && dok && yi < half;
+        const uint32_t y = yi < half ? 2 * yi + py : py;
         const uint32_t ym = y == 0 ? Y - 1 : y - 1;
         const uint32_t yp = y + 1 == Y ? 0 : y + 1;
         // y < 2^16 and rowb < 2^24: 24-bit multiplies are exact
         const uint32_t oy = __umul24(y, rowb), om = __umul24(ym, rowb), op = __umul24(yp, rowb);
-        off[r] = oy + db;
-        const uint32_t a1 = ldw(c1p, om + db), a1o = ldw(c1p, om + ddb);
-        const uint32_t a2 = ldw(c1p, op + db), a2o = ldw(c1p, op + ddb);
-        const uint32_t b1 = ldw(c0p, oy + db), b1o = ldw(c0p, oy + ddb);
-        const uint32_t b2 = ldw(c2p, oy + db), b2o = ldw(c2p, oy + ddb);
-        const uint32_t e1 = ldw(c0p, om + db), e2 = ldw(c0p, op + db);
-        const uint32_t e3 = ldw(c2p, om + db), e4 = ldw(c2p, op + db);
-        A[r] = ldw(c1p, oy + db);
-        S[r] = (a1 + a2) + (b1 + b2) + ((shifted(left, a1, a1o) + shifted(left, a2, a2o)) +
-                                        (shifted(left, b1, b1o) + shifted(left, b2, b2o))) +
-               ((e1 + e2) + (e3 + e4));
+        uint32_t a = 0x01010101u, sum = 0;
+        if (zok) {
+            const uint32_t a1 = ldw(c1p, om + db), a1o = ldw(c1p, om + ddb);
+            const uint32_t a2 = ldw(c1p, op + db), a2o = ldw(c1p, op + ddb);
+            const uint32_t b1 = ldw(c0p, oy + db), b1o = ldw(c0p, oy + ddb);
+            const uint32_t b2 = ldw(c2p, oy + db), b2o = ldw(c2p, oy + ddb);
+            const uint32_t e1 = ldw(c0p, om + db), e2 = ldw(c0p, op + db);
+            const uint32_t e3 = ldw(c2p, om + db), e4 = ldw(c2p, op + db);
+            a = ldw(c1p, oy + db);
+            sum = (a1 + a2) + (b1 + b2) + ((shifted(left, a1, a1o) + shifted(left, a2, a2o)) +
+                                           (shifted(left, b1, b1o) + shifted(left, b2, b2o))) +
+                  ((e1 + e2) + (e3 + e4));
+        }
+        A[r] = a;
+        S[r] = sum;
+        need[r] = ok && ((~a & 0x01010101u) != 0u);
     }
-    const uint32_t cz = z * Y * nd;  // Philox counter word 0 of row (z, 0), dword 0
+    if (tid < kTableWords)
+        tab[tid] = tabv;
+    if (tid == 0) {
+        t_sh = tv;
+        run_sh = runv;
+    }
+    // per (row, wave) counts of occupied slots
+    uint32_t pos[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        const uint32_t a = A[r];
-        const uint32_t occ = ~a & 0x01010101u;  // 1 in each byte of an occupied site
-        if (!ok[r] || !occ)
-            continue;
+        const uint64_t m = __ballot(need[r]);
+        pos[r] = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (lane == 0)
+            wcnt[r * (NT / 64) + wid] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < RY * (NT / 64); ++k) {
+            const uint32_t c = wcnt[k];
+            wcnt[k] = run;
+            run += c;
+        }
+        wcnt[RY * (NT / 64)] = run;
+    }
+    __syncthreads();
+    if (!run_sh)
+        return false;  // uniform: the film's schedule is finished
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        if (need[r]) {
+            const uint32_t i = wcnt[r * (NT / 64) + wid] + pos[r];
+            lA[i] = A[r];
+            lS[i] = S[r];
+            lslot[i] = (uint16_t)(r * NT + tid);
+        }
+    }
+    __syncthreads();
+    const uint32_t n_items = wcnt[RY * (NT / 64)];
+    const uint32_t t = t_sh;
+    const uint32_t cz = z * Y * nd;  // Philox counter word 0 of row (z, 0), dword 0
+    for (uint32_t i = tid; i < n_items; i += NT) {
+        const uint32_t slot = lslot[i];
+        const uint32_t a = lA[i], sum = lS[i];
+        const uint32_t r = slot / NT, st = slot % NT;
+        const uint32_t y = 2 * ((by * RY + r) * TY + st / TX) + py;
+        const uint32_t dd = bx * TX + st % TX;
+        const uint32_t k4 = cz + y * nd + dd;
         uint32_t u[4];
-        philox(cz + off[r] / 4u, t, L.replica, sigma, L.key0, L.key1, u);
-        // table index per byte: n + 12 + 25 [s = +1]  (<= 49)
-        const uint32_t key = S[r] + ((a >> 1) & 0x01010101u) * 25u;
+        philox(k4, t, L.replica, sigma, L.key0, L.key1, u);
+        const uint32_t occ = ~a & 0x01010101u;
+        const uint32_t key = sum + ((a >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1], <= 49
         uint32_t F = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t thr = tab[(key >> (8 * i)) & 0xFFu];
-            F |= ((u[i] < thr) | (thr == kSentinel)) ? (2u << (8 * i)) : 0u;
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
+            F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
         }
         F &= occ << 1;  // vacancies never flip
-        if (!F)
-            continue;
-        // observables: up spins flipped (byte 2 in a & F) and down spins flipped
-        const uint32_t fu = F & a, fd = F ^ fu;
-        const int cu = __popc(fu), cd = __popc(fd);
-        const uint32_t su = __builtin_amdgcn_sad_u8(S[r] & ((fu >> 1) * 0xFFu), 0u, 0u);
-        const uint32_t sd = __builtin_amdgcn_sad_u8(S[r] & ((fd >> 1) * 0xFFu), 0u, 0u);
-        dM += 2 * (cd - cu);
-        dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
-        acc += cu + cd;
-        *reinterpret_cast<uint32_t *>(c1p + off[r]) = a ^ F;
+        if (F) {
+            // up spins flipped: byte 2 in a & F; down spins flipped: the rest of F
+            const uint32_t fu = F & a, fd = F ^ fu;
+            const int cu = __popc(fu), cd = __popc(fd);
+            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            dM += 2 * (cd - cu);
+            dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
+            acc += cu + cd;
+            *reinterpret_cast<uint32_t *>(c1p + __umul24(y, rowb) + dd * 4u) = a ^ F;
+        }
     }
+    return true;
 }
 
 // ---------------------------------------------------------------------------
