@@ -44,6 +44,8 @@ def bench_plain(cfg, h, fmt, steps, warmup, tuning=None):
 
     lat = Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init, fmt=fmt)
     if tuning:
+        if len(tuning) > 4 and tuning[4] == 1:
+            lat.attach_items()
         lat.set_tuning(*tuning)
     n_occ = lat.observables()["n_occ"]
     if warmup:
@@ -72,8 +74,13 @@ def roofline_int8(lat, cfg, n_sweeps=40):
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_phase_i8", "ms_per_launch": [round(v, 5) for v in ms],
+            "kernel": lat_kernel_name(lat), "ms_per_launch": [round(v, 5) for v in ms],
             "bytes_per_launch": int(bytes_per_launch)}
+
+
+def lat_kernel_name(lat):
+    t = lat.get_tuning()
+    return "k_phase_i8_list" if t[4] == 1 else "k_phase_i8"
 
 
 def tune_plain(cfg, h, fmt):
@@ -246,7 +253,7 @@ def main():
     if not args.no_tune:
         t0 = time.perf_counter()
         tune_info = tune_plain(cfg, h, 0)
-        tuning = tuple(tune_info["tiling"]) + (tune_info["use_graph"],)
+        tuning = tuple(tune_info["tiling"]) + (tune_info["use_graph"], tune_info["kernel"])
         log("plain tuning %.1fs: %s" % (time.perf_counter() - t0, tune_info))
     lat, n_occ, sweeps, wall, gpu_ms, recs = bench_plain(cfg, h, 0, args.steps, args.warmup, tuning)
     value = n_occ * sweeps / (gpu_ms * 1e-3)
@@ -259,7 +266,7 @@ def main():
     extra = {"tuning": tune_info}
     if not args.no_extra:
         tb = None if args.no_tune else tune_plain(cfg, h, 1)
-        tbt = None if tb is None else tuple(tb["tiling"]) + (tb["use_graph"],)
+        tbt = None if tb is None else tuple(tb["tiling"]) + (tb["use_graph"], tb["kernel"])
         lat_b, n_occ_b, sw_b, wall_b, gpu_ms_b, recs_b = bench_plain(cfg, h, 1, min(args.steps, 40), 2, tbt)
         extra["bitpack"] = {"value": round(n_occ_b * sw_b / (gpu_ms_b * 1e-3), 1),
                             "unit": "spin-flip attempts/s", "steps": min(args.steps, 40),

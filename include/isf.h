@@ -107,11 +107,13 @@ typedef struct {
 } isf_obs;
 
 /* Launch shape of the sweep kernels.  Every shape gives the same trajectory. */
+enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1 };
 typedef struct {
     uint32_t tile_x;    /* dwords (4 sites) per block row: 16, 32 or 64 */
     uint32_t tile_y;    /* active rows per block: tile_x * tile_y = 256 */
-    uint32_t rows_per_thread; /* 1, 2 or 4 */
+    uint32_t rows_per_thread; /* 1, 2 or 4 (TILES); items per thread 1 or 2 (LIST) */
     uint32_t use_graph; /* 1: replay schedules as HIP graphs, 0: plain launches */
+    uint32_t kernel;    /* ISF_KERNEL_TILES, or ISF_KERNEL_LIST (INT8 with items attached) */
 } isf_tuning;
 
 typedef struct isf_lattice isf_lattice;
@@ -173,6 +175,18 @@ int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube_host, uint64_t swee
 /* Acceptance thresholds for (T, h_num): out[0][n+12] for S = -1 and
  * out[1][n+12] for S = +1, n in [-12, 12]; 0xFFFFFFFF means always accepted. */
 int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]);
+
+/* Occupied-dword lists (INT8 only).  Occupancy never changes, so for each
+ * sublattice the dwords (4 compact sites) holding an occupied site can be
+ * listed once; the list kernel then gives every block exactly the same number
+ * of such dwords (balanced work whatever the film's shape) and never loads
+ * all-vacant regions.  isf_items_bytes gives the size of the lists for this
+ * film (the caller allocates a device buffer of at least that size, 256-byte
+ * aligned, and keeps it alive with the lattice); isf_attach_items builds and
+ * uploads them and selects ISF_KERNEL_LIST.  EINVAL if the film's coordinates
+ * do not fit the 32-bit item encoding, ESTATE for BITPACK. */
+int32_t isf_items_bytes(const isf_lattice *lat, uint64_t *bytes);
+int32_t isf_attach_items(isf_lattice *lat, void *items_dev, uint64_t bytes);
 
 /* Choose the launch shape for a lattice (validated; EINVAL if unsupported). */
 int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *tuning);

@@ -48,7 +48,10 @@ class Obs(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_uint32), ("tile_y", ctypes.c_uint32), ("rows_per_thread", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32)]
+                ("use_graph", ctypes.c_uint32), ("kernel", ctypes.c_uint32)]
+
+
+KERNEL_TILES, KERNEL_LIST = 0, 1
 
 
 EXPORTS = {
@@ -91,6 +94,8 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.POINTER(Record)), ctypes.c_int32]),
     "isf_time_launches": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint32)]),
+    "isf_items_bytes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "isf_attach_items": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
     "isf_recount": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]),
 }

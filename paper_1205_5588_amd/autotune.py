@@ -19,7 +19,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from ._lib import BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8
+from ._lib import BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST, KERNEL_TILES
 
 TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
@@ -63,27 +63,37 @@ class TuningCache:
             json.dump(self.data, fh, indent=1, sort_keys=True)
 
 
-def lookup(X: int, Y: int, Z: int, fmt: int, cache: Optional[TuningCache] = None) -> Tuple[int, int, int, bool]:
+def lookup(X: int, Y: int, Z: int, fmt: int, cache: Optional[TuningCache] = None) -> tuple:
     cache = cache or TuningCache()
     hit = cache.get(shape_key(X, Y, Z, fmt))
     if hit:
-        return tuple(hit["tiling"]) + (bool(hit["use_graph"]),)
-    return default_tiling(X, fmt) + (True,)
+        return tuple(hit["tiling"]) + (bool(hit["use_graph"]), int(hit.get("kernel", KERNEL_TILES)))
+    return default_tiling(X, fmt) + (True, KERNEL_TILES)
+
+
+LIST_CANDIDATES = [(64, 4, 1, KERNEL_LIST), (64, 4, 2, KERNEL_LIST)]
 
 
 def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,
-                 warmup: int = 8, candidates: Optional[Sequence[Tuple[int, int, int]]] = None,
-                 graphs: Sequence[bool] = (True, False)) -> dict:
-    """Time every launch shape on fresh copies of one film; returns the best and all timings."""
+                 warmup: int = 8, candidates: Optional[Sequence[Tuple[int, ...]]] = None,
+                 graphs: Sequence[bool] = (True, False), lists: bool = True) -> dict:
+    """Time every launch shape on fresh copies of one film; returns the best and all timings.
+
+    Candidates are (tile_x, tile_y, rows_per_thread[, kernel]); for INT8 films
+    the occupied-dword list kernel is tried too (lists=True)."""
     import torch
 
-    cands = list(candidates or TILINGS[fmt])
+    cands = [tuple(c) + ((KERNEL_TILES,) if len(c) == 3 else ()) for c in (candidates or TILINGS[fmt])]
+    if lists and fmt == FORMAT_INT8 and candidates is None:
+        cands += LIST_CANDIDATES
     ref_recs = ref_spins = None
     timings: List[dict] = []
     for tl in cands:
         for g in graphs:
             lat = make()
-            lat.set_tuning(tl[0], tl[1], tl[2], g)
+            if tl[3] == KERNEL_LIST:
+                lat.attach_items()
+            lat.set_tuning(tl[0], tl[1], tl[2], g, tl[3])
             lat.run_schedule([(T, h_num, warmup, 0)])
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
@@ -98,12 +108,12 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
                 ref_recs, ref_spins = recs, spins
             elif not (np.array_equal(recs, ref_recs) and np.array_equal(spins, ref_spins)):
                 raise AssertionError("launch shape %s graph=%s changed the trajectory" % (tl, g))
-            timings.append({"tiling": list(tl), "use_graph": g, "ms_per_sweep": ms / sweeps})
+            timings.append({"tiling": list(tl[:3]), "kernel": int(tl[3]), "use_graph": g, "ms_per_sweep": ms / sweeps})
             lat.close()
             del lat
     best = min(timings, key=lambda r: r["ms_per_sweep"])
-    return {"tiling": best["tiling"], "use_graph": best["use_graph"], "ms_per_sweep": best["ms_per_sweep"],
-            "all": timings}
+    return {"tiling": best["tiling"], "kernel": best["kernel"], "use_graph": best["use_graph"],
+            "ms_per_sweep": best["ms_per_sweep"], "all": timings}
 
 
 def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list], fmt: int,

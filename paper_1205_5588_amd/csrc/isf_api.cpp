@@ -25,6 +25,7 @@ hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, ui
 void batch_grid_i8(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz);
 bool tiling_supported(const Tiling &tl);
 hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
+hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s);
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s);
 hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s);
@@ -146,6 +147,8 @@ struct isf_lattice {
     hipGraphExec_t graph;
     uint32_t graph_sweeps;
     Tiling graph_tiling;
+    // occupied-dword lists attached (INT8)
+    bool items_attached;
 };
 
 struct isf_batch {
@@ -166,8 +169,13 @@ int32_t set_device_of(const isf_lattice *lat) {
 }
 
 int32_t launch_phase(const isf_lattice *lat, uint32_t sigma) {
-    hipError_t e = lat->d.format == ISF_FORMAT_INT8 ? launch_phase_i8(lat->L, lat->tiling, sigma, lat->stream)
-                                                    : launch_phase_bp(lat->L, lat->tiling, sigma, lat->stream);
+    hipError_t e;
+    if (lat->d.format == ISF_FORMAT_INT8 && lat->tiling.kernel == ISF_KERNEL_LIST)
+        e = launch_phase_i8_list(lat->L, lat->tiling.ry, spin_bytes_of(&lat->d) < (1ull << 32), sigma, lat->stream);
+    else if (lat->d.format == ISF_FORMAT_INT8)
+        e = launch_phase_i8(lat->L, lat->tiling, sigma, lat->stream);
+    else
+        e = launch_phase_bp(lat->L, lat->tiling, sigma, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "phase launch failed: %s", hipGetErrorString(e));
     return ISF_OK;
@@ -231,7 +239,7 @@ int32_t build_graph(isf_lattice *lat) {
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     if (lat->use_graph && lat->stream && n >= kGraphSweeps) {
         if (!lat->graph || lat->graph_tiling.tx != lat->tiling.tx || lat->graph_tiling.ty != lat->tiling.ty ||
-            lat->graph_tiling.ry != lat->tiling.ry) {
+            lat->graph_tiling.ry != lat->tiling.ry || lat->graph_tiling.kernel != lat->tiling.kernel) {
             int32_t rc = build_graph(lat);
             if (rc)
                 return rc;
@@ -386,7 +394,7 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     lat->aux = al;
     lat->aux_dev = static_cast<uint8_t *>(aux_dev);
     lat->stream = static_cast<hipStream_t>(stream);
-    lat->tiling = Tiling{64, 4, 2};
+    lat->tiling = Tiling{64, 4, 2, ISF_KERNEL_TILES};
     lat->use_graph = true;
     if (hipGetDevice(&lat->device) != hipSuccess) {
         delete lat;
@@ -447,10 +455,19 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
         return rc;
     if (!t)
         return fail(ISF_EINVAL, "null tuning");
-    Tiling tl{t->tile_x, t->tile_y, t->rows_per_thread};
-    const bool ok = lat->d.format == ISF_FORMAT_INT8 ? tiling_supported(tl) : tiling_supported_bp(tl);
-    if (!ok)
-        return fail(ISF_EINVAL, "unsupported tiling %ux%ux%u", tl.tx, tl.ty, tl.ry);
+    Tiling tl{t->tile_x, t->tile_y, t->rows_per_thread, t->kernel};
+    if (tl.kernel == ISF_KERNEL_LIST) {
+        if (lat->d.format != ISF_FORMAT_INT8 || !lat->items_attached)
+            return fail(ISF_ESTATE, "the list kernel needs an INT8 film with occupied-dword lists attached");
+        if (tl.ry != 1 && tl.ry != 2)
+            return fail(ISF_EINVAL, "list kernel: %u entries per thread (1 or 2)", tl.ry);
+    } else if (tl.kernel != ISF_KERNEL_TILES) {
+        return fail(ISF_EINVAL, "unknown kernel %u", tl.kernel);
+    } else {
+        const bool ok = lat->d.format == ISF_FORMAT_INT8 ? tiling_supported(tl) : tiling_supported_bp(tl);
+        if (!ok)
+            return fail(ISF_EINVAL, "unsupported tiling %ux%ux%u", tl.tx, tl.ty, tl.ry);
+    }
     lat->tiling = tl;
     lat->use_graph = t->use_graph != 0;
     return ISF_OK;
@@ -466,6 +483,100 @@ int32_t isf_get_tuning(const isf_lattice *lat, isf_tuning *t) {
     t->tile_y = lat->tiling.ty;
     t->rows_per_thread = lat->tiling.ry;
     t->use_graph = lat->use_graph;
+    t->kernel = lat->tiling.kernel;
+    return ISF_OK;
+}
+
+namespace {
+uint32_t bits_for(uint32_t v) {  // bits needed to hold values 0..v
+    uint32_t b = 0;
+    while (b < 32 && (v >> b))
+        ++b;
+    return b;
+}
+
+// Occupied-dword lists of the four sublattices from the device spins.
+int32_t build_items(isf_lattice *lat, std::vector<uint32_t> &items, uint32_t n[4], uint32_t &ybits,
+                    uint32_t &dbits) {
+    const isf_desc &d = lat->d;
+    if (d.format != ISF_FORMAT_INT8)
+        return fail(ISF_ESTATE, "occupied-dword lists exist for INT8 films only");
+    const uint32_t Y = d.Y, Z = d.Z, nd = d.X / 8;
+    const uint32_t zbits = bits_for(Z - 1);
+    ybits = bits_for(Y - 1);
+    dbits = bits_for(nd - 1);
+    if (zbits + ybits + dbits > 32)
+        return fail(ISF_EINVAL, "film coordinates need %u bits, more than a 32-bit list entry",
+                    zbits + ybits + dbits);
+    std::vector<uint32_t> buf((size_t)(Z + 2) * Y * nd);
+    HIP_TRY(hipMemcpyAsync(buf.data(), lat->L.spins, buf.size() * 4, hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    items.clear();
+    for (uint32_t s = 0; s < 4; ++s) {
+        const size_t before = items.size();
+        for (uint32_t z = s >> 1; z < Z; z += 2)
+            for (uint32_t y = s & 1u; y < Y; y += 2) {
+                const uint32_t *row = &buf[((size_t)(z + 1) * Y + y) * nd];
+                for (uint32_t j = 0; j < nd; ++j)
+                    if (row[j] != 0x01010101u)
+                        items.push_back((((z << ybits) | y) << dbits) | j);
+            }
+        n[s] = (uint32_t)(items.size() - before);
+    }
+    return ISF_OK;
+}
+}  // namespace
+
+int32_t isf_items_bytes(const isf_lattice *lat, uint64_t *bytes) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(ISF_EINVAL, "null output");
+    isf_lattice *l = const_cast<isf_lattice *>(lat);
+    if ((rc = set_device_of(l)))
+        return rc;
+    std::vector<uint32_t> items;
+    uint32_t n[4], yb, db;
+    if ((rc = build_items(l, items, n, yb, db)))
+        return rc;
+    *bytes = std::max<uint64_t>(256, (uint64_t)items.size() * 4);
+    return ISF_OK;
+}
+
+int32_t isf_attach_items(isf_lattice *lat, void *dev, uint64_t bytes) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!dev)
+        return fail(ISF_EINVAL, "null items buffer");
+    if ((uintptr_t)dev & 255)
+        return fail(ISF_EINVAL, "items buffer must be 256-byte aligned");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    std::vector<uint32_t> items;
+    uint32_t n[4], yb, db;
+    if ((rc = build_items(lat, items, n, yb, db)))
+        return rc;
+    if (bytes < (uint64_t)items.size() * 4)
+        return fail(ISF_ENOSPC, "items buffer of %llu bytes < %llu", (unsigned long long)bytes,
+                    (unsigned long long)items.size() * 4);
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(dev, items.data(), items.size() * 4, hipMemcpyHostToDevice, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    LatDev &L = lat->L;
+    L.items = static_cast<const uint32_t *>(dev);
+    uint32_t off = 0;
+    for (int s = 0; s < 4; ++s) {
+        L.n_items[s] = n[s];
+        L.items_off[s] = off;
+        off += n[s];
+    }
+    L.ybits = yb;
+    L.dbits = db;
+    lat->items_attached = true;
+    lat->tiling = Tiling{lat->tiling.tx, lat->tiling.ty, 1, ISF_KERNEL_LIST};
+    drop_graph(lat);
     return ISF_OK;
 }
 

@@ -77,6 +77,11 @@ struct LatDev {
     uint32_t replica;
     uint32_t format;
     uint32_t pad;
+    // occupied-dword lists (INT8): item = (((z << ybits) | y) << dbits) | d, per sublattice
+    const uint32_t *items;
+    uint32_t n_items[4];
+    uint32_t items_off[4];
+    uint32_t ybits, dbits;
 };
 
 // Aux buffer layout.
@@ -88,8 +93,11 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
     AuxLayout a;
     auto up = [](uint64_t v, uint64_t al) { return (v + al - 1) / al * al; };
     a.off_state = 0;
-    a.off_slots = up(sizeof(DevState), 256);
-    a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 256);
+    // the atomic slots get their own 4 KiB blocks, away from the state that every
+    // block of every launch reads (sharing a 4 KiB block with it slowed every
+    // sublattice launch by ~3 us on MI355X)
+    a.off_slots = up(sizeof(DevState), 4096);
+    a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 4096);
     a.off_tables = up(a.off_steps + sizeof(StepDesc) * max_steps, 256);
     a.off_records = up(a.off_tables + sizeof(uint32_t) * kTableWords * max_steps, 256);
     a.total = up(a.off_records + sizeof(isf_record) * max_steps, 256);
@@ -99,6 +107,7 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
 // Launch shape of the phase kernels.
 struct Tiling {
     uint32_t tx, ty, ry;  // threads along a row (dwords / words), threads across rows, rows per thread
+    uint32_t kernel;      // ISF_KERNEL_TILES or ISF_KERNEL_LIST (ry = list entries per thread)
 };
 
 // One film in a batched launch: its description and where its blocks start.

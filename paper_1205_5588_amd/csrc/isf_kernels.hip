@@ -56,6 +56,111 @@ __global__ __launch_bounds__(TX *TY) void k_phase_i8_batch(const BatchEntry *__r
 }
 
 // --------------------------------------------------------------------------
+// One sublattice phase over the film's list of occupied dwords (INT8).  Each
+// thread takes IPT consecutive-by-block list entries; every block holds
+// exactly 256 * IPT entries (the last one fewer), so the work per block is the
+// same wherever the film is dense or empty.  Entries are in row-major order,
+// so a wave's loads stay coalesced along runs of occupied dwords.  kSmall:
+// the spin buffer is below 4 GiB and byte offsets fit 32 bits.
+template <int IPT, bool kSmall>
+__global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma) {
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh;
+    const uint32_t tid = threadIdx.x;
+    uint32_t tabv = 0, tv = 0;
+    if (tid < kTableWords)
+        tabv = L.st->cur_table[tid];
+    if (tid == 0)
+        tv = (uint32_t)L.st->t;
+    const uint32_t n = L.n_items[sigma];
+    const uint32_t *items = L.items + L.items_off[sigma];
+    const uint32_t Y = L.Y, nd = L.nd, rowb = nd * 4u;
+    const size_t planeb = (size_t)Y * rowb;
+    const bool left = (((sigma & 1u) ^ (sigma >> 1)) == 0);
+    const uint32_t dbits = L.dbits, ybits = L.ybits;
+    const uint32_t dmask = (1u << dbits) - 1u, ymask = (1u << ybits) - 1u;
+    char *base = reinterpret_cast<char *>(L.spins);
+
+    uint32_t A[IPT], S[IPT], pos[IPT];
+    size_t self_off[IPT];
+    bool ok[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t idx = (blockIdx.x * IPT + k) * 256u + tid;
+        ok[k] = idx < n;
+        const uint32_t it = n ? items[ok[k] ? idx : 0u] : 0u;
+        const uint32_t d = it & dmask, y = (it >> dbits) & ymask, z = it >> (dbits + ybits);
+        const uint32_t ym = y == 0 ? Y - 1 : y - 1;
+        const uint32_t yp = y + 1 == Y ? 0 : y + 1;
+        const uint32_t db = d * 4u;
+        const uint32_t ddb = (left ? (d == 0 ? nd - 1 : d - 1) : (d + 1 == nd ? 0 : d + 1)) * 4u;
+        const uint32_t oy = __umul24(y, rowb), om = __umul24(ym, rowb), op = __umul24(yp, rowb);
+        const char *p0, *p2;
+        char *p1;
+        if (kSmall) {
+            const uint32_t pl = (uint32_t)planeb;
+            p1 = base + (uint32_t)((z + 1) * pl);
+        } else {
+            p1 = base + (size_t)(z + 1) * planeb;
+        }
+        p0 = p1 - planeb;
+        p2 = p1 + planeb;
+        uint32_t a = 0x01010101u, sum = 0;
+        if (n) {
+            const uint32_t a1 = ldw(p1, om + db), a1o = ldw(p1, om + ddb);
+            const uint32_t a2 = ldw(p1, op + db), a2o = ldw(p1, op + ddb);
+            const uint32_t b1 = ldw(p0, oy + db), b1o = ldw(p0, oy + ddb);
+            const uint32_t b2 = ldw(p2, oy + db), b2o = ldw(p2, oy + ddb);
+            const uint32_t e1 = ldw(p0, om + db), e2 = ldw(p0, op + db);
+            const uint32_t e3 = ldw(p2, om + db), e4 = ldw(p2, op + db);
+            a = ldw(p1, oy + db);
+            sum = (a1 + a2) + (b1 + b2) + ((shifted(left, a1, a1o) + shifted(left, a2, a2o)) +
+                                           (shifted(left, b1, b1o) + shifted(left, b2, b2o))) +
+                  ((e1 + e2) + (e3 + e4));
+        }
+        A[k] = a;
+        S[k] = sum;
+        self_off[k] = (size_t)(p1 - base) + oy + db;
+        pos[k] = __umul24(__umul24(z, Y) + y, nd) + d;  // Philox counter word 0 = k div 4
+    }
+    if (tid < kTableWords)
+        tab[tid] = tabv;
+    if (tid == 0)
+        t_sh = tv;
+    __syncthreads();
+    const uint32_t t = t_sh;
+    int dM = 0, dE = 0, acc = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t a = A[k], sum = S[k];
+        const uint32_t occ = ~a & 0x01010101u;
+        if (!ok[k] || !occ)
+            continue;
+        uint32_t u[4];
+        philox(pos[k], t, L.replica, sigma, L.key0, L.key1, u);
+        const uint32_t key = sum + ((a >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1]
+        uint32_t F = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
+            F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
+        }
+        F &= occ << 1;
+        if (F) {
+            const uint32_t fu = F & a, fd = F ^ fu;
+            const int cu = __popc(fu), cd = __popc(fd);
+            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            dM += 2 * (cd - cu);
+            dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
+            acc += cu + cd;
+            *reinterpret_cast<uint32_t *>(base + self_off[k]) = a ^ F;
+        }
+    }
+    finish_block<256>(L, dM, dE, acc, blockIdx.x);
+}
+
+// --------------------------------------------------------------------------
 // Sweep end of one film (one wave), or of every running film of a batch (one
 // wave per film), launched after the last sublattice of each sweep.
 __global__ __launch_bounds__(64) void k_sweep_end(LatDev L) { sweep_end<false>(L); }
@@ -184,6 +289,22 @@ hipError_t launch_sweep_end(const LatDev &L, hipStream_t s) {
 
 hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep_end_batch, dim3(n_ents), dim3(64), 0, s, ents_dev, n_ents);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s) {
+    const uint32_t per_block = 256u * ipt;
+    const uint32_t blocks = std::max<uint32_t>(1u, (L.n_items[sigma] + per_block - 1) / per_block);
+    if (ipt == 1 && small)
+        hipLaunchKernelGGL((k_phase_i8_list<1, true>), dim3(blocks), dim3(256), 0, s, L, sigma);
+    else if (ipt == 1)
+        hipLaunchKernelGGL((k_phase_i8_list<1, false>), dim3(blocks), dim3(256), 0, s, L, sigma);
+    else if (ipt == 2 && small)
+        hipLaunchKernelGGL((k_phase_i8_list<2, true>), dim3(blocks), dim3(256), 0, s, L, sigma);
+    else if (ipt == 2)
+        hipLaunchKernelGGL((k_phase_i8_list<2, false>), dim3(blocks), dim3(256), 0, s, L, sigma);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -199,7 +199,12 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
     const uint32_t n_items = wcnt[RY * (NT / 64)];
     const uint32_t t = t_sh;
     const uint32_t cz = z * Y * nd;  // Philox counter word 0 of row (z, 0), dword 0
-    for (uint32_t i = tid; i < n_items; i += NT) {
+    // Wave w of this block takes the items of wave slot (w + rot): the partial
+    // last 64-item group goes to a different wave in neighbouring blocks, so the
+    // extra pass is spread over the SIMDs of a CU instead of piling onto one.
+    const uint32_t rot = (bx + by + bz) % (NT / 64);
+    const uint32_t i0 = ((wid + rot) % (NT / 64)) * 64u + lane;
+    for (uint32_t i = i0; i < n_items; i += NT) {
         const uint32_t slot = lslot[i];
         const uint32_t a = lA[i], sum = lS[i];
         const uint32_t r = slot / NT, st = slot % NT;

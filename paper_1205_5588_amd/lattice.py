@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8, INIT_DOWN, INIT_RANDOM,
-                   INIT_UP, MAX_STEPS, Desc, Obs, Record, Step, Tuning, check)
+                   INIT_UP, KERNEL_LIST, KERNEL_TILES, MAX_STEPS, Desc, Obs, Record, Step, Tuning, check)
 
 RECORD_FIELDS = ("M", "E", "sum_M", "sum_absM", "sum_E", "accepted")
 
@@ -63,7 +63,7 @@ class Lattice:
 
     def __init__(self, heights: np.ndarray, Z: int, seed: int, replica: int = 0, init: int = INIT_UP,
                  fmt: int = FORMAT_INT8, device: Optional[str] = None, stream=None,
-                 spin_buf=None, aux_buf=None):
+                 spin_buf=None, aux_buf=None, items: bool = False):
         torch = _torch()
         h = np.ascontiguousarray(heights, dtype=np.uint8)
         self.Y, self.X = h.shape
@@ -91,6 +91,18 @@ class Lattice:
                                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self._h = handle
         self._n_loaded = 0
+        self.items_buf = None
+        if items and self.fmt == FORMAT_INT8:
+            self.attach_items()
+
+    def attach_items(self) -> None:
+        """Build the film's occupied-dword lists on the device and select the list kernel."""
+        torch = _torch()
+        nb = ctypes.c_uint64()
+        check(_lib.load().isf_items_bytes(self.handle, ctypes.byref(nb)))
+        self.items_buf = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(_lib.load().isf_attach_items(self.handle, self.items_buf.data_ptr(), int(nb.value)))
 
     # ------------------------------------------------------------------ lifecycle
     def close(self) -> None:
@@ -111,14 +123,15 @@ class Lattice:
         return self._h
 
     # ------------------------------------------------------------------ tuning
-    def set_tuning(self, tile_x: int = 64, tile_y: int = 4, rows_per_thread: int = 2, use_graph: bool = True):
-        t = Tuning(tile_x, tile_y, rows_per_thread, 1 if use_graph else 0)
+    def set_tuning(self, tile_x: int = 64, tile_y: int = 4, rows_per_thread: int = 2, use_graph: bool = True,
+                   kernel: int = KERNEL_TILES):
+        t = Tuning(tile_x, tile_y, rows_per_thread, 1 if use_graph else 0, int(kernel))
         check(_lib.load().isf_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         check(_lib.load().isf_get_tuning(self.handle, ctypes.byref(t)))
-        return (t.tile_x, t.tile_y, t.rows_per_thread, bool(t.use_graph))
+        return (t.tile_x, t.tile_y, t.rows_per_thread, bool(t.use_graph), int(t.kernel))
 
     # ------------------------------------------------------------------ runs
     def run_schedule(self, steps: Sequence[Tuple[float, int, int, int]]) -> np.ndarray:

@@ -170,6 +170,8 @@ def test_invalid_arguments_raise(isf):
     with pytest.raises(IsfError):
         g.set_tuning(128, 2, 1, False)
     with pytest.raises(IsfError):
+        g.set_tuning(64, 4, 1, False, 1)      # list kernel before lists are attached
+    with pytest.raises(IsfError):
         g.set_spins(np.full((2, 8, 16), 5, dtype=np.int8), 0)
 
 
@@ -300,3 +302,41 @@ def test_batched_incremental_chunks(isf):
     for (h, Z, s, r, sc), lat in zip(films, lats):
         o = cpu.Film(h, Z, s, r, init=2)
         np.testing.assert_array_equal(lat.records(), np.array([o.run(*st).as_tuple() for st in sc]))
+
+
+# ------------------------------------------------------------------ occupied-dword list kernel
+@pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (8, 4, 1), (264, 10, 2), (328, 46, 6)])
+@pytest.mark.parametrize("ipt", [1, 2])
+def test_list_kernel_matches_oracle(isf, X, Y, Z, ipt):
+    h = _rand_h((Y, X), Z, 7 * X + Y + Z)
+    g, o = _pair(isf, h, Z, 24680, replica=6, init=2)
+    g.attach_items()
+    g.set_tuning(64, 4, ipt, ipt == 1, 1)
+    assert g.get_tuning()[4] == 1
+    _say("list kernel", X, Y, Z, ipt)
+    steps = [(2.5, 30, 70, 0), (0.8, -45, 4, 1), (9.0, 0, 66, 6), (4.0, -7, 5, 2), (1e-3, 241, 1, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_list_kernel_empty_and_full_films(isf):
+    _say("list kernel degenerate")
+    for h, Z in ((np.zeros((8, 16), dtype=np.uint8), 3), (np.full((16, 32), 4, dtype=np.uint8), 4),
+                 (np.ones((32, 64), dtype=np.uint8), 1)):
+        g, o = _pair(isf, h, Z, 5, init=2)
+        g.attach_items()
+        np.testing.assert_array_equal(g.run_sweeps(2.2, 10, 9, 3), o.run(2.2, 10, 9, 3).as_tuple())
+        _assert_same(g, o)
+
+
+def test_list_kernel_large_prefix(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.attach_items()
+    _say("list kernel, large film prefix")
+    hs = c.h_nums[:1]
+    np.testing.assert_array_equal(g.ramp_field(c.T, hs, 12), cpu.hysteresis(o, c.T, hs, 12))
+    _assert_same(g, o)
