@@ -107,13 +107,16 @@ typedef struct {
 } isf_obs;
 
 /* Launch shape of the sweep kernels.  Every shape gives the same trajectory. */
-enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1 };
+enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1, ISF_KERNEL_SWEEP = 2 };
 typedef struct {
     uint32_t tile_x;    /* dwords (4 sites) per block row: 16, 32 or 64 */
-    uint32_t tile_y;    /* active rows per block: tile_x * tile_y = 256 */
-    uint32_t rows_per_thread; /* 1, 2 or 4 (TILES); items per thread 1 or 2 (LIST) */
+    uint32_t tile_y;    /* TILES/LIST: active rows per block, tile_x * tile_y = 256;
+                           SWEEP: rows of the block's tile (16x16, 32x8, 32x16, 32x32, 64x8, 64x16) */
+    uint32_t rows_per_thread; /* 1, 2 or 4 (TILES); items per thread 1 or 2 (LIST); waves per block 4, 8 or 16 (SWEEP) */
     uint32_t use_graph; /* 1: replay schedules as HIP graphs, 0: plain launches */
-    uint32_t kernel;    /* ISF_KERNEL_TILES, or ISF_KERNEL_LIST (INT8 with items attached) */
+    uint32_t kernel;    /* ISF_KERNEL_TILES; ISF_KERNEL_LIST (INT8 with items attached); ISF_KERNEL_SWEEP
+                           (INT8: one launch per sweep, the block's tile and a halo in LDS; EINVAL if the
+                           shape's LDS for the film's Z exceeds the device's per-block limit) */
 } isf_tuning;
 
 typedef struct isf_lattice isf_lattice;
@@ -244,7 +247,9 @@ int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, c
  * as plain launches, with a pair of HIP events around every sublattice
  * launch on the lattice's stream; waits, then writes the mean duration of
  * the launches of sublattice s to ms_per_launch[s] (milliseconds) and the
- * number of sweeps run to *swept.  The trajectory is the same as isf_advance. */
+ * number of sweeps run to *swept.  With ISF_KERNEL_SWEEP the whole-sweep
+ * launch is reported in ms_per_launch[0] and the other three entries are the
+ * (empty) event pairs' durations.  The trajectory is the same as isf_advance. */
 int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms_per_launch[4], uint32_t *swept);
 
 /* Full recount of M and E_bond from the spins on the device (not the tracked

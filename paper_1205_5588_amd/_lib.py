@@ -51,7 +51,7 @@ class Tuning(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("kernel", ctypes.c_uint32)]
 
 
-KERNEL_TILES, KERNEL_LIST = 0, 1
+KERNEL_TILES, KERNEL_LIST, KERNEL_SWEEP = 0, 1, 2
 
 
 EXPORTS = {

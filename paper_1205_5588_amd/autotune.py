@@ -19,7 +19,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from ._lib import BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST, KERNEL_TILES
+from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST, KERNEL_SWEEP,
+                   KERNEL_TILES, IsfError)
 
 TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
@@ -72,6 +73,10 @@ def lookup(X: int, Y: int, Z: int, fmt: int, cache: Optional[TuningCache] = None
 
 
 LIST_CANDIDATES = [(64, 4, 1, KERNEL_LIST), (64, 4, 2, KERNEL_LIST)]
+# whole-sweep kernel: (tile dwords, tile rows, waves per block); shapes whose LDS
+# does not fit the film's Z are skipped
+SWEEP_CANDIDATES = [(32, 16, 8, KERNEL_SWEEP), (16, 16, 4, KERNEL_SWEEP), (32, 8, 4, KERNEL_SWEEP),
+                    (64, 8, 8, KERNEL_SWEEP), (32, 32, 8, KERNEL_SWEEP), (32, 32, 16, KERNEL_SWEEP)]
 
 
 def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,
@@ -80,12 +85,13 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
     """Time every launch shape on fresh copies of one film; returns the best and all timings.
 
     Candidates are (tile_x, tile_y, rows_per_thread[, kernel]); for INT8 films
-    the occupied-dword list kernel is tried too (lists=True)."""
+    the occupied-dword list kernel (lists=True) and the whole-sweep kernel are
+    tried too.  Shapes the library rejects for this film are skipped."""
     import torch
 
     cands = [tuple(c) + ((KERNEL_TILES,) if len(c) == 3 else ()) for c in (candidates or TILINGS[fmt])]
-    if lists and fmt == FORMAT_INT8 and candidates is None:
-        cands += LIST_CANDIDATES
+    if fmt == FORMAT_INT8 and candidates is None:
+        cands += (LIST_CANDIDATES if lists else []) + SWEEP_CANDIDATES
     ref_recs = ref_spins = None
     timings: List[dict] = []
     for tl in cands:
@@ -93,7 +99,11 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
             lat = make()
             if tl[3] == KERNEL_LIST:
                 lat.attach_items()
-            lat.set_tuning(tl[0], tl[1], tl[2], g, tl[3])
+            try:
+                lat.set_tuning(tl[0], tl[1], tl[2], g, tl[3])
+            except IsfError:
+                lat.close()
+                continue
             lat.run_schedule([(T, h_num, warmup, 0)])
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)

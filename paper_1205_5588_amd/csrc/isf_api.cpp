@@ -27,6 +27,13 @@ bool tiling_supported(const Tiling &tl);
 hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
 hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s);
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
+hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
+                                const uint8_t *lists, hipStream_t s);
+hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
+uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
+uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
+uint64_t halo_lists_bytes(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t Z);
+uint64_t halo_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
 hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s);
 hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s);
 
@@ -109,6 +116,19 @@ uint64_t spin_bytes_of(const isf_desc *d) {
     return (uint64_t)(d->Z + 2) * d->Y * 2 * (W / 32) * 4;
 }
 
+// The aux buffer: device state, slots, schedule, tables and records, then (INT8)
+// the spare copy of the spins and the per-tile lists used by the whole-sweep
+// kernel (sized for the shape that needs the most).
+uint64_t spare_offset() { return (aux_layout(ISF_MAX_STEPS).total + 4095) / 4096 * 4096; }
+
+uint64_t lists_offset(const isf_desc *d) { return (spare_offset() + spin_bytes_of(d) + 4095) / 4096 * 4096; }
+
+uint64_t aux_bytes_of(const isf_desc *d) {
+    if (d->format != ISF_FORMAT_INT8)
+        return aux_layout(ISF_MAX_STEPS).total;
+    return lists_offset(d) + halo_lists_bytes_max(d->X / 8, d->Y, d->Z);
+}
+
 // Threshold of Eq. (8) for an uphill move with dE = q/10: floor(2^32 exp(-dE/T)).
 uint32_t threshold_of(int32_t q, double T) {
     if (q <= 0)
@@ -149,6 +169,17 @@ struct isf_lattice {
     Tiling graph_tiling;
     // occupied-dword lists attached (INT8)
     bool items_attached;
+    // second copy of the spins for the whole-sweep kernel (INT8), at the end of
+    // the aux buffer; cur_spare: the current state is in the spare copy;
+    // spare_ready: the spare copy holds the film's vacancies
+    uint8_t *spare;
+    bool cur_spare;
+    bool spare_ready;
+    // per-tile lists of occupied dwords of the whole-sweep kernel (after the
+    // spare copy in the aux buffer), valid for lists_tiling when lists_ready
+    uint8_t *lists;
+    bool lists_ready;
+    Tiling lists_tiling;
 };
 
 struct isf_batch {
@@ -188,13 +219,61 @@ int32_t launch_end(const isf_lattice *lat) {
     return ISF_OK;
 }
 
-// One sweep = four sublattice launches and the one-wave sweep-end launch.
-int32_t enqueue_sweeps_plain(const isf_lattice *lat, uint64_t n) {
+// The whole-sweep kernel reads one copy of the spins and writes the other.
+// The spare copy gets the film's layout (its vacancies) once, before its
+// first use; after a whole sweep the state may sit in the spare copy, and
+// settle() moves it back before anything else reads or writes the spins.
+int32_t prepare_spare(isf_lattice *lat) {
+    if (!lat->spare_ready) {
+        HIP_TRY(hipMemcpyAsync(lat->spare, lat->L.spins, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice,
+                               lat->stream));
+        lat->spare_ready = true;
+    }
+    const Tiling &tl = lat->tiling, &lt = lat->lists_tiling;
+    if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty) {
+        hipError_t e = launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "list launch failed: %s", hipGetErrorString(e));
+        lat->lists_ready = true;
+        lat->lists_tiling = tl;
+    }
+    return ISF_OK;
+}
+
+int32_t settle(isf_lattice *lat) {
+    if (lat->cur_spare) {
+        HIP_TRY(hipMemcpyAsync(lat->L.spins, lat->spare, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice,
+                               lat->stream));
+        lat->cur_spare = false;
+    }
+    return ISF_OK;
+}
+
+int32_t launch_whole_sweep(isf_lattice *lat) {
+    uint8_t *a = lat->L.spins, *b = lat->spare;
+    hipError_t e = lat->cur_spare ? launch_sweep_i8_halo(lat->L, lat->tiling, b, a, lat->lists, lat->stream)
+                                  : launch_sweep_i8_halo(lat->L, lat->tiling, a, b, lat->lists, lat->stream);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
+    lat->cur_spare = !lat->cur_spare;
+    return ISF_OK;
+}
+
+// One sweep = four sublattice launches (or one whole-sweep launch) and the
+// one-wave sweep-end launch.
+int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
+    const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
     for (uint64_t i = 0; i < n; ++i) {
-        for (uint32_t s = 0; s < 4; ++s) {
-            int32_t rc = launch_phase(lat, s);
+        if (whole) {
+            int32_t rc = launch_whole_sweep(lat);
             if (rc)
                 return rc;
+        } else {
+            for (uint32_t s = 0; s < 4; ++s) {
+                int32_t rc = launch_phase(lat, s);
+                if (rc)
+                    return rc;
+            }
         }
         int32_t rc = launch_end(lat);
         if (rc)
@@ -237,6 +316,19 @@ int32_t build_graph(isf_lattice *lat) {
 }
 
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
+    int32_t rc0;
+    if (lat->tiling.kernel == ISF_KERNEL_SWEEP) {
+        if ((rc0 = prepare_spare(lat)))
+            return rc0;
+        // graphs hold an even number of whole sweeps and start from the main copy
+        if (lat->cur_spare && n > 0) {
+            if ((rc0 = enqueue_sweeps_plain(lat, 1)))
+                return rc0;
+            --n;
+        }
+    } else if ((rc0 = settle(lat))) {
+        return rc0;
+    }
     if (lat->use_graph && lat->stream && n >= kGraphSweeps) {
         if (!lat->graph || lat->graph_tiling.tx != lat->tiling.tx || lat->graph_tiling.ty != lat->tiling.ty ||
             lat->graph_tiling.ry != lat->tiling.ry || lat->graph_tiling.kernel != lat->tiling.kernel) {
@@ -349,7 +441,7 @@ int32_t isf_lattice_bytes(const isf_desc *d, uint64_t *spin_bytes, uint64_t *aux
     if (!spin_bytes || !aux_bytes)
         return fail(ISF_EINVAL, "null output pointer");
     *spin_bytes = spin_bytes_of(d);
-    *aux_bytes = aux_layout(ISF_MAX_STEPS).total;
+    *aux_bytes = aux_bytes_of(d);
     return ISF_OK;
 }
 
@@ -378,9 +470,9 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
         return fail(ISF_EINVAL, "unknown init mode %d", init);
     const uint64_t need_spin = spin_bytes_of(d);
     const AuxLayout al = aux_layout(ISF_MAX_STEPS);
-    if (spin_bytes < need_spin || aux_bytes < al.total)
+    if (spin_bytes < need_spin || aux_bytes < aux_bytes_of(d))
         return fail(ISF_ENOSPC, "buffers too small: need %llu + %llu bytes", (unsigned long long)need_spin,
-                    (unsigned long long)al.total);
+                    (unsigned long long)aux_bytes_of(d));
     if (((uintptr_t)spin_dev & 255) || ((uintptr_t)aux_dev & 255))
         return fail(ISF_EINVAL, "device buffers must be 256-byte aligned");
     for (uint64_t i = 0, n = (uint64_t)d->X * d->Y; i < n; ++i)
@@ -402,6 +494,8 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     }
     LatDev &L = lat->L;
     L.spins = static_cast<uint8_t *>(spin_dev);
+    lat->spare = d->format == ISF_FORMAT_INT8 ? lat->aux_dev + spare_offset() : nullptr;
+    lat->lists = d->format == ISF_FORMAT_INT8 ? lat->aux_dev + lists_offset(d) : nullptr;
     L.st = reinterpret_cast<DevState *>(lat->aux_dev + al.off_state);
     L.slots = reinterpret_cast<Slot *>(lat->aux_dev + al.off_slots);
     L.steps = reinterpret_cast<StepDesc *>(lat->aux_dev + al.off_steps);
@@ -461,6 +555,17 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
             return fail(ISF_ESTATE, "the list kernel needs an INT8 film with occupied-dword lists attached");
         if (tl.ry != 1 && tl.ry != 2)
             return fail(ISF_EINVAL, "list kernel: %u entries per thread (1 or 2)", tl.ry);
+    } else if (tl.kernel == ISF_KERNEL_SWEEP) {
+        if (lat->d.format != ISF_FORMAT_INT8 || !lat->spare)
+            return fail(ISF_EINVAL, "the whole-sweep kernel needs an INT8 film");
+        const uint32_t lds = halo_lds_bytes(tl.tx, tl.ty, lat->d.Z);
+        if (lds == 0 || (tl.ry != 4 && tl.ry != 8 && tl.ry != 16))
+            return fail(ISF_EINVAL, "unsupported whole-sweep shape %ux%u with %u waves", tl.tx, tl.ty, tl.ry);
+        int max_lds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
+        if (lds > (uint32_t)max_lds - 1024u || halo_region_dwords(tl.tx, tl.ty, lat->d.Z) > 65536u)
+            return fail(ISF_EINVAL, "whole-sweep shape %ux%u needs %u bytes of LDS for Z = %u (limit %d)", tl.tx,
+                        tl.ty, lds, lat->d.Z, max_lds);
     } else if (tl.kernel != ISF_KERNEL_TILES) {
         return fail(ISF_EINVAL, "unknown kernel %u", tl.kernel);
     } else {
@@ -762,6 +867,8 @@ int32_t isf_read_spins(isf_lattice *lat, int8_t *cube) {
         return fail(ISF_EINVAL, "null output");
     if ((rc = set_device_of(lat)))
         return rc;
+    if ((rc = settle(lat)))
+        return rc;
     const isf_desc &d = lat->d;
     std::vector<uint8_t> buf(spin_bytes_of(&d));
     HIP_TRY(hipMemcpyAsync(buf.data(), lat->L.spins, buf.size(), hipMemcpyDeviceToHost, lat->stream));
@@ -795,6 +902,8 @@ int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube, uint64_t sweeps) {
     if (!cube)
         return fail(ISF_EINVAL, "null input");
     if ((rc = set_device_of(lat)))
+        return rc;
+    if ((rc = settle(lat)))
         return rc;
     const isf_desc &d = lat->d;
     std::vector<uint8_t> buf(spin_bytes_of(&d));
@@ -851,10 +960,19 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
     for (auto &e : ev)
         HIP_TRY(hipEventCreate(&e));
     int32_t status = ISF_OK;
+    const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
+    if ((rc = whole ? prepare_spare(lat) : settle(lat))) {
+        for (auto &e : ev)
+            (void)hipEventDestroy(e);
+        return rc;
+    }
     for (uint32_t i = 0; i < n && status == ISF_OK; ++i) {
         for (uint32_t s = 0; s < 4 && status == ISF_OK; ++s) {
             (void)hipEventRecord(ev[8 * i + 2 * s], lat->stream);
-            status = launch_phase(lat, s);
+            if (!whole)
+                status = launch_phase(lat, s);
+            else if (s == 0)
+                status = launch_whole_sweep(lat);
             (void)hipEventRecord(ev[8 * i + 2 * s + 1], lat->stream);
         }
         if (status == ISF_OK)
@@ -892,6 +1010,8 @@ int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E) {
     if (!M || !E)
         return fail(ISF_EINVAL, "null output");
     if ((rc = set_device_of(lat)))
+        return rc;
+    if ((rc = settle(lat)))
         return rc;
     int64_t cnt[4];
     if ((rc = recount(lat, cnt)))
@@ -981,13 +1101,22 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
         return ISF_OK;
     }
     const uint32_t format = lats[0]->d.format;
-    const Tiling tl = lats[0]->tiling;
+    // batches run the one-launch-per-sublattice tiles; other kernels fall back to the default shape
+    const Tiling tl = lats[0]->tiling.kernel == ISF_KERNEL_TILES ? lats[0]->tiling : Tiling{64, 4, 2, ISF_KERNEL_TILES};
     for (uint32_t i = 0; i < n; ++i) {
         if (!lats[i])
             return fail(ISF_EINVAL, "null lattice %u", i);
         if (lats[i]->d.format != format)
             return fail(ISF_ESTATE, "lattices of a batch must share one format");
     }
+    // batch kernels work on the main copy of the spins
+    for (uint32_t i = 0; i < n; ++i)
+        if (lats[i]->cur_spare) {
+            int32_t rc = settle(lats[i]);
+            if (rc)
+                return rc;
+            HIP_TRY(hipStreamSynchronize(lats[i]->stream));
+        }
     // the staging area may still be read by the previous copy
     HIP_TRY(hipEventSynchronize(b->staged));
     uint64_t sweeps = 0;

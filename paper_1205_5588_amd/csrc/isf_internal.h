@@ -93,9 +93,8 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
     AuxLayout a;
     auto up = [](uint64_t v, uint64_t al) { return (v + al - 1) / al * al; };
     a.off_state = 0;
-    // the atomic slots get their own 4 KiB blocks, away from the state that every
-    // block of every launch reads (sharing a 4 KiB block with it slowed every
-    // sublattice launch by ~3 us on MI355X)
+    // the atomic slots get their own 4 KiB page, apart from the state that every
+    // block of every launch reads
     a.off_slots = up(sizeof(DevState), 4096);
     a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 4096);
     a.off_tables = up(a.off_steps + sizeof(StepDesc) * max_steps, 256);

@@ -16,11 +16,11 @@
 // Observables: each accepted flip changes M by -2 s_old and E_bond by
 // +2 s_old n.  Blocks reduce these in registers and LDS and add them with
 // relaxed agent-scope atomics to one of 64 slots (spread over 128-byte lines).
-// The last block of the last sublattice of a sweep (found with an atomic
-// counter) folds the slots into M and E, advances the sweep counter, updates
-// the step's sums and, at the end of a step, writes its record and stages the
-// next step's threshold table.  The host never has to read anything back
-// between sweeps, and every launch of a schedule has the same arguments.
+// After the last sublattice of a sweep a one-wave launch (k_sweep_end) folds
+// the slots into M and E, advances the sweep counter, updates the step's sums
+// and, at the end of a step, writes its record and stages the next step's
+// threshold table.  The host never has to read anything back between sweeps,
+// and every launch of a schedule has the same arguments.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -1,0 +1,501 @@
+// One whole Metropolis sweep of an INT8 film per launch (all four sublattice
+// phases, Section 5 steps 1-3 with the acceptance rule of Eq. 8).
+//
+// A block owns a tile of TXD dwords x TYR rows of every plane z.  It loads the
+// tile into LDS together with a halo of HX dwords and HY rows on each side
+// (x and y are periodic, so halo rows and dwords wrap), runs the four phases
+// sigma = 0..3 on the LDS copy, and writes the tile to the other buffer of a
+// ping-pong pair: the launch reads one copy of the film and writes the other,
+// because blocks that start late must still see the halo values from before
+// the sweep.  The halo is updated too, redundantly with the neighbouring
+// blocks, so that the tile sees the same neighbour values as the four-launch
+// sweep:
+//
+//   every site's 12 neighbours lie at most one row away in y and at most one
+//   byte (compact column) away in x, so a value computed in phase k is right
+//   wherever all its neighbours were right before phase k.  Starting from
+//   the loaded values (right on the whole region), phase k is evaluated on
+//   rows within 3 - k of the tile and, for k < 3, on one halo dword on each
+//   side; its results are then right within 3 - k rows and 4 - k bytes of the
+//   tile, which covers everything phase k + 1 reads.  Phase 3 runs on the
+//   tile alone.
+//
+// Draws are keyed by (site dword, sweep, replica, sigma) only, so the halo
+// copies draw the same numbers as the owning block, and the trajectory is
+// identical, bit for bit, to the one-launch-per-sublattice kernels.  Only the
+// tile's own flips enter the observables.
+//
+// The sweep is bound by integer ALU work (Philox and the neighbour sums), so
+// the per-site instruction count is what matters:
+//   * vacant dwords are skipped: each block's occupied dwords per phase are
+//     listed once per film and tiling by k_sweep_lists (occupancy is
+//     static) and kept in HBM; a sweep copies its block's lists into LDS next
+//     to the region;
+//   * a list entry is the dword's region index; the row index follows with
+//     one multiply, and a per-row table gives the Philox counter base and
+//     whether the row belongs to the tile;
+//   * the 13 LDS reads of a dword use one base address and immediate offsets;
+//   * two entries per iteration keep two gathers in flight.
+// HBM traffic per sweep: each block reads (TXD + 2 HX)(TYR + 2 HY) dwords per
+// plane plus its lists and writes its tile's occupied dwords.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "isf_device.h"
+
+namespace isf {
+
+namespace {
+
+constexpr int kHX = 2;  // halo dwords on each side along x
+constexpr int kHY = 4;  // halo rows on each side along y
+constexpr uint32_t kVacant = 0x01010101u;
+
+// Region geometry and the candidate slots of each phase: rows ry = r0, r0+2,
+// ... (nry), planes z = pz, pz+2, ... (nz), dwords cx0 .. cx0 + ncx - 1.
+template <int TXD, int TYR>
+struct Geo {
+    static constexpr int RX = TXD + 2 * kHX;
+    static constexpr int RYN = TYR + 2 * kHY;
+    static constexpr int PL = RX * RYN;
+    __host__ __device__ static constexpr int lo(int s) { return kHY - (3 - s); }
+    __host__ __device__ static constexpr int hi(int s) { return kHY + TYR + (3 - s); }
+    // first row >= lo with parity py (region rows have the parity of their global row: y0 and kHY are even)
+    __host__ __device__ static constexpr int r0(int s) { return lo(s) + ((lo(s) ^ (s & 1)) & 1); }
+    __host__ __device__ static constexpr int nry(int s) { return (hi(s) - r0(s) + 1) / 2; }
+    __host__ __device__ static constexpr int cx0(int s) { return s < 3 ? kHX - 1 : kHX; }
+    __host__ __device__ static constexpr int ncx(int s) { return s < 3 ? TXD + 2 : TXD; }
+    __host__ __device__ static constexpr uint32_t nz(int s, uint32_t Z) { return (Z - (uint32_t)(s >> 1) + 1) / 2; }
+    __host__ __device__ static constexpr uint32_t cand(int s, uint32_t Z) {
+        return (uint32_t)(nry(s) * ncx(s)) * nz(s, Z);
+    }
+    // list capacity of phase s, in entries: a multiple of 4 so that lists stay 8-byte aligned
+    __host__ __device__ static constexpr uint32_t cap(int s, uint32_t Z) { return (cand(s, Z) + 3u) & ~3u; }
+    __host__ __device__ static constexpr uint32_t list_off(int s, uint32_t Z) {
+        uint32_t o = 0;
+        for (int k = 0; k < s; ++k)
+            o += cap(k, Z);
+        return o;
+    }
+    __host__ __device__ static constexpr uint32_t cap_total(uint32_t Z) { return list_off(4, Z); }
+    // HBM record of one tile: 4 uint32 counts, then the four lists of uint16 region indices
+    __host__ __device__ static constexpr uint32_t rec_bytes(uint32_t Z) {
+        return (16u + 2u * cap_total(Z) + 255u) & ~255u;
+    }
+    // LDS: region words | row table (uint2 per region row) | ymap | dmap | lists
+    __host__ __device__ static constexpr uint32_t off_rowk(uint32_t Z) { return 4u * (Z + 2) * PL; }
+    __host__ __device__ static constexpr uint32_t off_ymap(uint32_t Z) { return off_rowk(Z) + 8u * (Z + 2) * RYN; }
+    __host__ __device__ static constexpr uint32_t off_dmap(uint32_t Z) { return off_ymap(Z) + 4u * RYN; }
+    __host__ __device__ static constexpr uint32_t off_lst(uint32_t Z) { return off_dmap(Z) + 4u * RX; }
+    __host__ __device__ static constexpr uint32_t lds_bytes(uint32_t Z) { return off_lst(Z) + 2u * cap_total(Z); }
+};
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t per_xcd) {
+    // Blocks are dealt to the 8 XCDs round robin; block b takes tile
+    // (b % 8) * per_xcd + b / 8, so each XCD works on a contiguous band of
+    // tiles and the halo rows shared by neighbouring tiles stay in its L2.
+    return (b & 7u) * per_xcd + (b >> 3);
+}
+
+}  // namespace
+
+// Lists of occupied dwords per phase for every tile (run once per film and
+// tiling; occupancy never changes).  One block per tile; the order of entries
+// within a list is arbitrary.
+template <int TXD, int TYR>
+__global__ __launch_bounds__(256) void k_sweep_lists(LatDev L, uint32_t nbx, uint32_t per_xcd, uint8_t *lists) {
+    using G = Geo<TXD, TYR>;
+    __shared__ uint32_t cnt[4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t Y = L.Y, Z = L.Z, nd = L.nd;
+    const uint32_t tile = tile_of_block(blockIdx.x, per_xcd);
+    const uint32_t nby = (Y + TYR - 1) / TYR;
+    if (tile >= nbx * nby)
+        return;
+    const uint32_t bx = tile % nbx, by = tile / nbx;
+    const int d0 = (int)(bx * TXD), y0 = (int)(by * TYR);
+    uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
+    uint16_t *ent = reinterpret_cast<uint16_t *>(rec + 16);
+    if (tid < 4)
+        cnt[tid] = 0;
+    __syncthreads();
+    const char *spins = reinterpret_cast<const char *>(L.spins);
+    const size_t rowb = (size_t)nd * 4u, planeb = (size_t)Y * rowb;
+    for (int s = 0; s < 4; ++s) {
+        const uint32_t n = G::cand(s, Z);
+        const uint32_t nr = (n + 255u) / 256u * 256u;
+        for (uint32_t c = tid; c < nr; c += 256) {
+            uint32_t ri = 0;
+            bool occ = false;
+            if (c < n) {
+                const uint32_t cx = G::cx0(s) + c % G::ncx(s);
+                const uint32_t q = c / G::ncx(s);
+                const uint32_t ry = G::r0(s) + 2 * (q % G::nry(s));
+                const uint32_t z = (uint32_t)(s >> 1) + 2 * (q / G::nry(s));
+                ri = ((z + 1) * G::RYN + ry) * G::RX + cx;
+                const int y = wrap_mod(y0 - kHY + (int)ry, (int)Y), d = wrap_mod(d0 - kHX + (int)cx, (int)nd);
+                const uint32_t v =
+                    *reinterpret_cast<const uint32_t *>(spins + (z + 1) * planeb + (size_t)y * rowb + (size_t)d * 4u);
+                occ = v != kVacant;
+            }
+            const uint64_t m = __ballot(occ);
+            if (m) {
+                const uint32_t pos =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                uint32_t base_i = 0;
+                if (lane == 0)
+                    base_i = atomicAdd(&cnt[s], (uint32_t)__popcll(m));
+                base_i = __builtin_amdgcn_readfirstlane(base_i);  // lane 0 is active here
+                if (occ)
+                    ent[G::list_off(s, Z) + base_i + pos] = (uint16_t)ri;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < 4)
+        reinterpret_cast<uint32_t *>(rec)[tid] = cnt[tid];
+}
+
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *__restrict__ src,
+                                                      uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
+                                                      uint32_t nbx, uint32_t per_xcd) {
+    using G = Geo<TXD, TYR>;
+    constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL;
+    extern __shared__ __align__(16) uint8_t smb[];
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh, run_sh;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t Y = L.Y, Z = L.Z, nd = L.nd;
+    const uint32_t np = Z + 2;
+    uint32_t *R = reinterpret_cast<uint32_t *>(smb);                       // [np][RYN][RX] dwords
+    uint2 *rowk = reinterpret_cast<uint2 *>(smb + G::off_rowk(Z));        // per region row: Philox base, ymap
+    uint32_t *ymap = reinterpret_cast<uint32_t *>(smb + G::off_ymap(Z));  // global row, bit 31: tile row
+    uint32_t *dmap = reinterpret_cast<uint32_t *>(smb + G::off_dmap(Z));  // global dword, bit 31: tile dword
+    uint16_t *lst = reinterpret_cast<uint16_t *>(smb + G::off_lst(Z));
+
+    const uint32_t b = blockIdx.x;
+    const uint32_t tile = tile_of_block(b, per_xcd);
+    const uint32_t nby = (Y + TYR - 1) / TYR;
+    if (tile >= nbx * nby)
+        return;  // uniform: grid padding to a multiple of 8
+    const uint32_t bx = tile % nbx, by = tile / nbx;
+    const uint32_t d0 = bx * TXD, y0 = by * TYR;
+    const uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
+    const uint4 cnt = *reinterpret_cast<const uint4 *>(rec);  // uniform: a scalar load
+
+    if (tid < kTableWords)
+        tab[tid] = L.st->cur_table[tid];
+    if (tid == 0) {
+        t_sh = (uint32_t)L.st->t;
+        run_sh = L.st->step < L.st->n_steps;
+    }
+    const uint32_t ynd = Y * nd;
+    for (uint32_t i = tid; i < np * RYN + RX; i += NT) {
+        if (i < np * RYN) {
+            const uint32_t p = i / RYN, ry = i % RYN;
+            const uint32_t y = (uint32_t)wrap_mod((int)(y0 + ry) - kHY, (int)Y);
+            const bool own = ry >= (uint32_t)kHY && ry < (uint32_t)(kHY + TYR) && y0 + ry - kHY < Y;
+            const uint32_t ym = y | (own ? 0x80000000u : 0u);
+            rowk[i] = make_uint2((p - 1) * ynd + y * nd, ym);  // p = 0 and np - 1 (padding) are never looked up
+            if (p == 0)
+                ymap[ry] = ym;
+        } else {
+            const uint32_t c = i - np * RYN;
+            const uint32_t d = (uint32_t)wrap_mod((int)(d0 + c) - kHX, (int)nd);
+            const bool own = c >= (uint32_t)kHX && c < (uint32_t)(kHX + TXD) && d0 + c - kHX < nd;
+            dmap[c] = d | (own ? 0x80000000u : 0u);
+        }
+    }
+
+    // This block's lists, HBM -> LDS (8-byte words; each list is 8-byte aligned).
+    {
+        const uint32_t c4[4] = {cnt.x, cnt.y, cnt.z, cnt.w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint32_t nw = (c4[s] + 3u) / 4u;
+            const uint2 *from = reinterpret_cast<const uint2 *>(rec + 16 + 2u * G::list_off(s, Z));
+            uint2 *to = reinterpret_cast<uint2 *>(lst + G::list_off(s, Z));
+            for (uint32_t i = tid; i < nw; i += NT)
+                to[i] = from[i];
+        }
+    }
+
+    // The region: planes 1..Z from the film, the padding planes are vacancies.
+    // Films at least as large as the region, with an even number of dwords per
+    // row, take 8-byte loads (dword pairs never straddle the periodic seam and
+    // stay 8-byte aligned) with the wrap done arithmetically, eight loads in
+    // flight per thread; other films take 4-byte loads with the wrap by modulo.
+    const uint32_t rowb = nd * 4u;
+    const size_t planeb = (size_t)Y * rowb;
+    const char *base = reinterpret_cast<const char *>(src);
+    const bool wide = (nd & 1u) == 0 && nd >= (uint32_t)RX && Y >= (uint32_t)RYN;  // uniform
+    if (wide) {
+        constexpr uint32_t RX2 = RX / 2, PL2 = PL / 2;
+        const uint32_t n = Z * PL2;
+        for (uint32_t i0 = 0; i0 < n; i0 += 8 * NT) {
+            uint2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t i = i0 + k * NT + tid;
+                if (i < n) {
+                    const uint32_t p = i / PL2 + 1, r = i % PL2;
+                    const uint32_t ry = r / RX2, cx = 2 * (r % RX2);
+                    int y = (int)(y0 + ry) - kHY, d = (int)(d0 + cx) - kHX;
+                    y += y < 0 ? (int)Y : 0;
+                    y -= y >= (int)Y ? (int)Y : 0;
+                    d += d < 0 ? (int)nd : 0;
+                    d -= d >= (int)nd ? (int)nd : 0;
+                    v[k] = *reinterpret_cast<const uint2 *>(base + p * planeb + (uint32_t)y * rowb + (uint32_t)d * 4u);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t i = i0 + k * NT + tid;
+                if (i < n) {
+                    const uint32_t p = i / PL2 + 1, r = i % PL2;
+                    *reinterpret_cast<uint2 *>(&R[p * PL + 2 * r]) = v[k];
+                }
+            }
+        }
+    } else {
+        const uint32_t n = Z * PL;
+#pragma unroll 4
+        for (uint32_t i = tid; i < n; i += NT) {
+            const uint32_t p = i / PL + 1, r = i % PL;
+            const uint32_t ry = r / RX, cx = r % RX;
+            const uint32_t y = (uint32_t)wrap_mod((int)(y0 + ry) - kHY, (int)Y);
+            const uint32_t d = (uint32_t)wrap_mod((int)(d0 + cx) - kHX, (int)nd);
+            R[p * PL + r] = *reinterpret_cast<const uint32_t *>(base + p * planeb + y * rowb + d * 4u);
+        }
+    }
+    for (uint32_t i = tid; i < (uint32_t)PL; i += NT) {
+        R[i] = kVacant;
+        R[(np - 1) * PL + i] = kVacant;
+    }
+    __syncthreads();
+    if (!run_sh)
+        return;  // uniform: the schedule is finished
+
+    int dM = 0, dE = 0, acc = 0;
+    const uint32_t t = t_sh;
+    const uint32_t c4[4] = {cnt.x, cnt.y, cnt.z, cnt.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const uint32_t n = c4[s];
+        const uint16_t *ls = lst + G::list_off(s, Z);
+        const bool left = ((s & 1) ^ (s >> 1)) == 0;  // (y + z) even: the shifted columns are j - 1
+        constexpr int kB = PL + RX;                    // offset of the dword from its gather base
+        const int o = left ? -1 : 1;
+        auto sh = [left](uint32_t cur, uint32_t other) {
+            return left ? __builtin_amdgcn_alignbyte(cur, other, 3) : __builtin_amdgcn_alignbyte(other, cur, 1);
+        };
+        // two entries per iteration: both gathers are issued before either flip is
+        // written, so their LDS latencies overlap (dwords of one phase share no bond)
+        for (uint32_t i = tid; i < n; i += 2 * NT) {
+            const bool two = i + NT < n;
+            uint32_t ri[2];
+            ri[0] = ls[i];
+            ri[1] = two ? ls[i + NT] : ri[0];
+            uint32_t a[2], sum[2], kb[2], ym[2], dm[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t q = ri[k];
+                const uint32_t row = q / RX, cx = q - row * RX;
+                const uint32_t *Rb = R + (q - kB);  // every offset below is >= 0
+                a[k] = Rb[kB];
+                const uint32_t a1 = Rb[kB - RX], a2 = Rb[kB + RX];
+                const uint32_t b1 = Rb[kB - PL], b2 = Rb[kB + PL];
+                const uint32_t a1o = Rb[kB - RX + o], a2o = Rb[kB + RX + o];
+                const uint32_t b1o = Rb[kB - PL + o], b2o = Rb[kB + PL + o];
+                const uint32_t e1 = Rb[0], e2 = Rb[kB - PL + RX];
+                const uint32_t e3 = Rb[kB + PL - RX], e4 = Rb[kB + PL + RX];
+                sum[k] = (a1 + a2) + (b1 + b2) + ((sh(a1, a1o) + sh(a2, a2o)) + (sh(b1, b1o) + sh(b2, b2o))) +
+                         ((e1 + e2) + (e3 + e4));
+                const uint2 rk = rowk[row];
+                kb[k] = rk.x;
+                ym[k] = rk.y;
+                dm[k] = dmap[cx];
+            }
+            uint32_t F[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                uint32_t u[4];
+                philox(kb[k] + (dm[k] & 0x7FFFFFFFu), t, L.replica, (uint32_t)s, L.key0, L.key1, u);
+                const uint32_t key = sum[k] + ((a[k] >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1], <= 49
+                uint32_t f = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // Downhill and level moves have the sentinel threshold 2^32 - 1, and
+                    // every uphill threshold is below 2^32 - 1 (T <= 1e6 and dE >= 0.1),
+                    // so with u clamped to 2^32 - 2 the single test u < thr is exact.
+                    const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
+                    f |= (min(u[j], 0xFFFFFFFEu) < thr) ? (2u << (8 * j)) : 0u;
+                }
+                F[k] = f & ((~a[k] & 0x01010101u) << 1);  // vacancies never flip
+            }
+            if (!two)
+                F[1] = 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (F[k]) {
+                    R[ri[k]] = a[k] ^ F[k];
+                    if ((ym[k] & dm[k]) >> 31) {  // a dword of this block's tile
+                        const uint32_t fu = F[k] & a[k], fd = F[k] ^ fu;
+                        const int cu = __popc(fu), cd = __popc(fd);
+                        const uint32_t su = __builtin_amdgcn_sad_u8(sum[k] & ((fu >> 1) * 0xFFu), 0u, 0u);
+                        const uint32_t sd = __builtin_amdgcn_sad_u8(sum[k] & ((fd >> 1) * 0xFFu), 0u, 0u);
+                        dM += 2 * (cd - cu);
+                        dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
+                        acc += cu + cd;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Write the tile's occupied dwords to the other buffer (8-byte stores on
+    // the wide path: a pair goes out if either dword holds an occupied site).
+    char *out = reinterpret_cast<char *>(dst);
+    if (wide) {
+        constexpr uint32_t TX2 = TXD / 2;
+        const uint32_t n = Z * TYR * TX2;
+        for (uint32_t i = tid; i < n; i += NT) {
+            const uint32_t cx = 2 * (i % TX2), q = i / TX2;
+            const uint32_t ry = q % TYR, p = q / TYR + 1;
+            const uint32_t y = y0 + ry, d = d0 + cx;
+            const uint2 v = *reinterpret_cast<const uint2 *>(&R[(p * RYN + ry + kHY) * RX + cx + kHX]);
+            if (y < Y && d < nd && (v.x != kVacant || v.y != kVacant))
+                *reinterpret_cast<uint2 *>(out + p * planeb + y * rowb + d * 4u) = v;
+        }
+    } else {
+        const uint32_t n = Z * TYR * TXD;
+        for (uint32_t i = tid; i < n; i += NT) {
+            const uint32_t cx = kHX + i % TXD, q = i / TXD;
+            const uint32_t ry = kHY + q % TYR, p = q / TYR + 1;
+            const uint32_t v = R[(p * RYN + ry) * RX + cx];
+            const uint32_t ym = ymap[ry], dm = dmap[cx];
+            if (((ym & dm) >> 31) && v != kVacant)
+                *reinterpret_cast<uint32_t *>(out + p * planeb + (ym & 0x7FFFFFFFu) * rowb + (dm & 0x7FFFFFFFu) * 4u) = v;
+        }
+    }
+    finish_block<NT>(L, dM, dE, acc, b);
+}
+
+namespace {
+
+template <int TXD, int TYR>
+void grid_of(const LatDev &L, uint32_t &nbx, uint32_t &per_xcd, uint32_t &tiles) {
+    nbx = (L.nd + TXD - 1) / TXD;
+    tiles = nbx * ((L.Y + TYR - 1) / TYR);
+    per_xcd = (tiles + 7) / 8;
+}
+
+template <int TXD, int TYR>
+hipError_t launch_halo_t(const LatDev &L, const uint8_t *src, uint8_t *dst, const uint8_t *lists, uint32_t nt,
+                         hipStream_t s) {
+    uint32_t nbx, per_xcd, tiles;
+    grid_of<TXD, TYR>(L, nbx, per_xcd, tiles);
+    const size_t lds = Geo<TXD, TYR>::lds_bytes(L.Z);
+    const dim3 grid(per_xcd * 8);
+    if (nt == 1024)
+        hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 1024>), grid, dim3(1024), lds, s, L, src, dst, lists, nbx,
+                           per_xcd);
+    else if (nt == 512)
+        hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 512>), grid, dim3(512), lds, s, L, src, dst, lists, nbx,
+                           per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 256>), grid, dim3(256), lds, s, L, src, dst, lists, nbx,
+                           per_xcd);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+hipError_t launch_lists_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
+    uint32_t nbx, per_xcd, tiles;
+    grid_of<TXD, TYR>(L, nbx, per_xcd, tiles);
+    hipLaunchKernelGGL((k_sweep_lists<TXD, TYR>), dim3(per_xcd * 8), dim3(256), 0, s, L, nbx, per_xcd, lists);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+uint64_t lists_bytes_t(uint32_t nd, uint32_t Y, uint32_t Z) {
+    const uint64_t tiles = (uint64_t)((nd + TXD - 1) / TXD) * ((Y + TYR - 1) / TYR);
+    return tiles * Geo<TXD, TYR>::rec_bytes(Z);
+}
+
+}  // namespace
+
+#define ISF_HALO_SHAPES(X) X(16, 16) X(32, 8) X(32, 16) X(32, 32) X(64, 8) X(64, 16)
+
+// Dynamic LDS bytes of the whole-sweep kernel for a film of Z planes, or 0 if
+// (tile_x, tile_y) is not a compiled shape.
+uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z) {
+#define ISF_CASE(A, B) \
+    if (tx == A && ty == B) \
+        return Geo<A, B>::lds_bytes(Z);
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return 0;
+}
+
+// Region dwords of the shape (list entries are 16-bit region indices).
+uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z) {
+    return (Z + 2) * (tx + 2 * kHX) * (ty + 2 * kHY);
+}
+
+// Bytes of the per-tile lists of a shape, and the most any shape whose region
+// indices fit 16 bits needs (the lists' place in the aux buffer is sized for it).
+uint64_t halo_lists_bytes(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t Z) {
+#define ISF_CASE(A, B) \
+    if (tx == A && ty == B) \
+        return lists_bytes_t<A, B>(nd, Y, Z);
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return 0;
+}
+
+uint64_t halo_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z) {
+    uint64_t m = 0;
+#define ISF_CASE(A, B) \
+    if (halo_region_dwords(A, B, Z) <= 65536u) \
+        m = std::max<uint64_t>(m, lists_bytes_t<A, B>(nd, Y, Z));
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return m;
+}
+
+// Build the per-tile lists of occupied dwords (reads the film's occupancy from L.spins).
+hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s) {
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_lists_t<A, B>(L, lists, s);
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
+}
+
+// One sweep reading the film from src and writing it to dst (both laid out
+// like the spin buffer; dst must already hold the film's vacancies), with the
+// lists built for the same tiling.
+hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
+                                const uint8_t *lists, hipStream_t s) {
+    const uint32_t nt = 64u * tl.ry;  // 4, 8 or 16 waves
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_halo_t<A, B>(L, src, dst, lists, nt, s);
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace isf

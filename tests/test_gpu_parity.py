@@ -340,3 +340,84 @@ def test_list_kernel_large_prefix(isf):
     hs = c.h_nums[:1]
     np.testing.assert_array_equal(g.ramp_field(c.T, hs, 12), cpu.hysteresis(o, c.T, hs, 12))
     _assert_same(g, o)
+
+
+# ------------------------------------------------------------------ whole-sweep kernel (tile + halo in LDS)
+SWEEP_SHAPES = [(72, 38, 5), (8, 4, 1), (264, 10, 2), (328, 46, 6), (520, 70, 9), (40, 6, 4)]
+SWEEP_TILINGS = [(32, 16, 4), (16, 16, 8), (64, 8, 4), (32, 32, 16), (32, 8, 4), (64, 16, 4)]
+
+
+@pytest.mark.parametrize("X,Y,Z", SWEEP_SHAPES)
+@pytest.mark.parametrize("tiling", SWEEP_TILINGS)
+def test_sweep_kernel_matches_oracle(isf, X, Y, Z, tiling):
+    h = _rand_h((Y, X), Z, 5 * X + 3 * Y + Z)
+    g, o = _pair(isf, h, Z, 13579, replica=4, init=2)
+    g.set_tuning(tiling[0], tiling[1], tiling[2], (X + Y) % 2 == 0, 2)
+    assert g.get_tuning()[4] == 2
+    _say("sweep kernel", X, Y, Z, tiling)
+    steps = [(2.5, 30, 66, 0), (0.8, -45, 4, 1), (9.0, 0, 3, 1), (4.0, -7, 5, 2), (1e-3, 241, 1, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_sweep_kernel_degenerate_films(isf):
+    _say("sweep kernel degenerate")
+    for h, Z in ((np.zeros((8, 16), dtype=np.uint8), 3), (np.full((16, 32), 4, dtype=np.uint8), 4),
+                 (np.ones((32, 64), dtype=np.uint8), 1), (np.full((4, 8), 2, dtype=np.uint8), 2)):
+        g, o = _pair(isf, h, Z, 5, init=2)
+        g.set_tuning(32, 16, 4, False, 2)
+        np.testing.assert_array_equal(g.run_sweeps(2.2, 10, 9, 3), o.run(2.2, 10, 9, 3).as_tuple())
+        _assert_same(g, o)
+
+
+def test_sweep_kernel_rejects_unsupported(isf):
+    from paper_1205_5588_amd._lib import IsfError
+
+    h = _rand_h((16, 128), 4, 1)
+    g = isf.Lattice(h, 4, 1, fmt=1)
+    with pytest.raises(IsfError):
+        g.set_tuning(32, 16, 4, False, 2)  # bit-packed film
+    g = isf.Lattice(h, 4, 1)
+    for bad in ((32, 12, 4), (48, 16, 4), (32, 16, 2), (32, 16, 32)):
+        with pytest.raises(IsfError):
+            g.set_tuning(bad[0], bad[1], bad[2], False, 2)
+    tall = isf.Lattice(np.full((16, 512), 64, dtype=np.uint8), 64, 1)
+    with pytest.raises(IsfError):
+        tall.set_tuning(64, 16, 4, False, 2)  # LDS of a 64-plane region exceeds the block limit
+    assert g.get_tuning()[4] == 0  # rejected shapes leave the previous tuning
+
+
+def test_sweep_kernel_large_prefix(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.set_tuning(32, 16, 4, True, 2)
+    _say("sweep kernel, large film prefix")
+    hs = c.h_nums[:1]
+    np.testing.assert_array_equal(g.ramp_field(c.T, hs, 12), cpu.hysteresis(o, c.T, hs, 12))
+    _assert_same(g, o)
+
+
+def test_sweep_kernel_equals_tiles_tscan_film(isf):
+    """Random start, high temperature (many flips) on the 512 x 512 x 5 film: sweep kernel == tile kernel."""
+    from isf_workloads import config_plain_tscan
+
+    c = config_plain_tscan()
+    h = c.heights()
+    a = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    b = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    b.set_tuning(16, 16, 8, True, 2)
+    _say("sweep kernel vs tiles, tscan film")
+    steps = [(12.0, 0, 40, 10), (5.0, 0, 30, 0), (3.0, 15, 70, 20)]
+    np.testing.assert_array_equal(a.run_schedule(steps), b.run_schedule(steps))
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    # timed launches follow the same trajectory
+    for lat in (a, b):
+        lat.schedule_load([(2.0, -20, 6, 0)])
+    a.advance(6)
+    ms, n = b.time_launches(6)
+    assert n == 6 and ms[0] > 0.0
+    np.testing.assert_array_equal(a.records(), b.records())
+    np.testing.assert_array_equal(a.spins(), b.spins())
