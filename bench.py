@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_LIST, KERNEL_SWEEP = 1, 2  # isf_tuning.kernel
 
 
 def log(*a):
@@ -65,22 +66,54 @@ def bench_plain(cfg, h, fmt, steps, warmup, tuning=None):
 
 
 def roofline_int8(lat, cfg, n_sweeps=40):
-    """Mean duration of the sublattice kernel from HIP events around every launch."""
+    """Mean duration of the dominant kernel from HIP events around every launch of it.
+
+    Algorithmic bytes per launch (N_c = X Y Z / 2 compact site bytes): a whole-sweep
+    launch reads every site byte once and writes it once (2 N_c); a sublattice
+    launch reads every site byte once (its quarter and the neighbours) and writes
+    its quarter (1.25 N_c)."""
     lat.schedule_load([(cfg.T, cfg.h_nums[0], n_sweeps, 0)])
     ms, n = lat.time_launches(n_sweeps)
-    mean_ms = sum(ms) / 4.0
     Nc = cfg.X * cfg.Y * cfg.Z // 2
-    bytes_per_launch = 1.25 * Nc  # read all N_c site bytes once, write the active quarter
+    if lat.get_tuning()[4] == KERNEL_SWEEP:
+        mean_ms, bytes_per_launch = ms[0], 2.0 * Nc
+        ms = ms[:1]
+    else:
+        mean_ms, bytes_per_launch = sum(ms) / 4.0, 1.25 * Nc
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
+    traffic = measured_traffic(lat_kernel_name(lat))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": lat_kernel_name(lat), "ms_per_launch": [round(v, 5) for v in ms],
             "bytes_per_launch": int(bytes_per_launch)}
 
 
+KERNEL_SOURCES = ("isf_sweep.hip", "isf_device.h", "isf_internal.h")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
+    known size) from the committed counter summary, or None when there is none or
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec:
+        return None
+    csrc = os.path.join(ROOT, "paper_1205_5588_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, n), "rb").read() for n in KERNEL_SOURCES)
+    if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
+        return None
+    return int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
+
+
 def lat_kernel_name(lat):
     t = lat.get_tuning()
-    return "k_phase_i8_list" if t[4] == 1 else "k_phase_i8"
+    return {KERNEL_LIST: "k_phase_i8_list", KERNEL_SWEEP: "k_sweep_i8_halo"}.get(t[4], "k_phase_i8")
 
 
 def tune_plain(cfg, h, fmt):
@@ -88,7 +121,7 @@ def tune_plain(cfg, h, fmt):
     from paper_1205_5588_amd.lattice import Lattice
 
     res = tune_lattice(lambda: Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init, fmt=fmt), fmt, cfg.T, cfg.h_nums[0],
-                       sweeps=48, warmup=4)
+                       sweeps=128, warmup=4)
     return res
 
 
@@ -248,7 +281,9 @@ def main():
     h = cfg.heights()
     log("height map %.2fs" % (time.perf_counter() - t0))
 
-    tuning = None
+    from paper_1205_5588_amd.autotune import lookup
+
+    tuning = lookup(cfg.X, cfg.Y, cfg.Z, 0)  # cached or heuristic shape, replaced by the tuner's pick
     tune_info = None
     if not args.no_tune:
         t0 = time.perf_counter()
@@ -263,7 +298,9 @@ def main():
     log("roofline:", roof)
     del lat
 
-    extra = {"tuning": tune_info}
+    extra = {"tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
+                        "tuned": tune_info is not None,
+                        "candidates": 0 if tune_info is None else len(tune_info["all"])}}
     if not args.no_extra:
         tb = None if args.no_tune else tune_plain(cfg, h, 1)
         tbt = None if tb is None else tuple(tb["tiling"]) + (tb["use_graph"], tb["kernel"])

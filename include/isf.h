@@ -248,8 +248,8 @@ int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, c
  * launch on the lattice's stream; waits, then writes the mean duration of
  * the launches of sublattice s to ms_per_launch[s] (milliseconds) and the
  * number of sweeps run to *swept.  With ISF_KERNEL_SWEEP the whole-sweep
- * launch is reported in ms_per_launch[0] and the other three entries are the
- * (empty) event pairs' durations.  The trajectory is the same as isf_advance. */
+ * launch is reported in ms_per_launch[0] and the other three entries are 0.
+ * The trajectory is the same as isf_advance. */
 int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms_per_launch[4], uint32_t *swept);
 
 /* Full recount of M and E_bond from the spins on the device (not the tracked

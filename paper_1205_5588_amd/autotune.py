@@ -28,6 +28,8 @@ TILINGS = {
     FORMAT_BITPACK: [(64, 4, 1), (64, 4, 2), (32, 8, 1), (32, 8, 2), (16, 16, 1), (16, 16, 2)],
 }
 
+GRAPH_SWEEPS = 64  # sweeps per captured graph in the library
+
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
@@ -36,13 +38,27 @@ def shape_key(X: int, Y: int, Z: int, fmt: int) -> str:
 
 
 def default_tiling(X: int, fmt: int) -> Tuple[int, int, int]:
-    """Heuristic for shapes not in the cache: widest tile that the row fills."""
+    """Heuristic sublattice-kernel shape for films not in the cache: widest tile that the row fills."""
     per_row = X // 8 if fmt == FORMAT_INT8 else X // 64
     if per_row >= 64:
         return (64, 4, 2) if fmt == FORMAT_INT8 else (64, 4, 1)
     if per_row >= 32:
         return (32, 8, 2) if fmt == FORMAT_INT8 else (32, 8, 1)
     return (16, 16, 2) if fmt == FORMAT_INT8 else (16, 16, 1)
+
+
+def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
+    """Heuristic (tile_x, tile_y, rows_or_waves, use_graph, kernel) for films not in the cache.
+
+    INT8 films whose planes fit the whole-sweep kernel's LDS take it (measured
+    fastest on MI355X for both the 512^2 x 5 and the 2048^2 x 8 films: large
+    tiles where the film is wide, 16 x 16 tiles on small films); others take
+    the sublattice tiles."""
+    if fmt == FORMAT_INT8 and Z <= 8:
+        if X // 8 >= 256 and Y >= 512:
+            return (32, 32, 16, True, KERNEL_SWEEP)
+        return (16, 16, 4, True, KERNEL_SWEEP)
+    return default_tiling(X, fmt) + (True, KERNEL_TILES)
 
 
 class TuningCache:
@@ -69,7 +85,7 @@ def lookup(X: int, Y: int, Z: int, fmt: int, cache: Optional[TuningCache] = None
     hit = cache.get(shape_key(X, Y, Z, fmt))
     if hit:
         return tuple(hit["tiling"]) + (bool(hit["use_graph"]), int(hit.get("kernel", KERNEL_TILES)))
-    return default_tiling(X, fmt) + (True, KERNEL_TILES)
+    return default_tuning(X, Y, Z, fmt)
 
 
 LIST_CANDIDATES = [(64, 4, 1, KERNEL_LIST), (64, 4, 2, KERNEL_LIST)]
@@ -104,7 +120,9 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
             except IsfError:
                 lat.close()
                 continue
-            lat.run_schedule([(T, h_num, warmup, 0)])
+            # warm up past one graph length (every candidate alike: the same trajectory)
+            # so that a graph is built before the timed region
+            lat.run_schedule([(T, h_num, warmup + GRAPH_SWEEPS, 0)])
             ev0 = torch.cuda.Event(enable_timing=True)
             ev1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()

@@ -956,9 +956,11 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
     if ((rc = set_device_of(lat)))
         return rc;
     const uint32_t n = (uint32_t)std::min<uint64_t>(n_sweeps, lat->sched_total - lat->sched_enqueued);
+    // timing-only events: no system-scope fence when they are recorded, so that
+    // the pairs measure the launch between them and not a cache write-back
     std::vector<hipEvent_t> ev(8 * (size_t)n);
     for (auto &e : ev)
-        HIP_TRY(hipEventCreate(&e));
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     int32_t status = ISF_OK;
     const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
     if ((rc = whole ? prepare_spare(lat) : settle(lat))) {
@@ -966,13 +968,11 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
             (void)hipEventDestroy(e);
         return rc;
     }
+    const uint32_t n_launch = whole ? 1 : 4;  // event pairs per sweep
     for (uint32_t i = 0; i < n && status == ISF_OK; ++i) {
-        for (uint32_t s = 0; s < 4 && status == ISF_OK; ++s) {
+        for (uint32_t s = 0; s < n_launch && status == ISF_OK; ++s) {
             (void)hipEventRecord(ev[8 * i + 2 * s], lat->stream);
-            if (!whole)
-                status = launch_phase(lat, s);
-            else if (s == 0)
-                status = launch_whole_sweep(lat);
+            status = whole ? launch_whole_sweep(lat) : launch_phase(lat, s);
             (void)hipEventRecord(ev[8 * i + 2 * s + 1], lat->stream);
         }
         if (status == ISF_OK)
@@ -984,7 +984,7 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         if (hipStreamSynchronize(lat->stream) != hipSuccess)
             status = fail(ISF_EHIP, "stream synchronisation failed");
         for (uint32_t i = 0; i < n && status == ISF_OK; ++i)
-            for (uint32_t s = 0; s < 4; ++s) {
+            for (uint32_t s = 0; s < n_launch; ++s) {
                 float m = 0.f;
                 if (hipEventElapsedTime(&m, ev[8 * i + 2 * s], ev[8 * i + 2 * s + 1]) != hipSuccess) {
                     status = fail(ISF_EHIP, "hipEventElapsedTime failed");
