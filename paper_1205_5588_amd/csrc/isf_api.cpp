@@ -28,7 +28,9 @@ hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
 hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s);
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
-                                const uint8_t *lists, hipStream_t s);
+                                const uint8_t *lists, uint32_t q, hipStream_t s);
+hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
+hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s);
 hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
 uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
@@ -180,6 +182,9 @@ struct isf_lattice {
     uint8_t *lists;
     bool lists_ready;
     Tiling lists_tiling;
+    // a run of whole-sweep launches is open: the schedule position lives in the
+    // parity-buffered positions until k_whole_flush hands it back
+    bool whole_active;
 };
 
 struct isf_batch {
@@ -240,7 +245,32 @@ int32_t prepare_spare(isf_lattice *lat) {
     return ISF_OK;
 }
 
+// Open a run of whole-sweep launches (before the first one is enqueued or captured).
+int32_t prime_whole(isf_lattice *lat) {
+    if (!lat->whole_active) {
+        hipError_t e = launch_whole_prime(lat->L, lat->cur_spare ? 1u : 0u, lat->stream);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "prime launch failed: %s", hipGetErrorString(e));
+        lat->whole_active = true;
+    }
+    return ISF_OK;
+}
+
+// Close the run: fold the last sweep, whose parity is the opposite of the next one's.
+int32_t flush_whole(isf_lattice *lat) {
+    if (lat->whole_active) {
+        hipError_t e = launch_whole_flush(lat->L, lat->cur_spare ? 0u : 1u, lat->stream);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "flush launch failed: %s", hipGetErrorString(e));
+        lat->whole_active = false;
+    }
+    return ISF_OK;
+}
+
 int32_t settle(isf_lattice *lat) {
+    int32_t rc = flush_whole(lat);  // the parity must be read before the spins move back
+    if (rc)
+        return rc;
     if (lat->cur_spare) {
         HIP_TRY(hipMemcpyAsync(lat->L.spins, lat->spare, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice,
                                lat->stream));
@@ -249,18 +279,19 @@ int32_t settle(isf_lattice *lat) {
     return ISF_OK;
 }
 
+// Sweep parity q = 1 when the current spins are in the spare copy.
 int32_t launch_whole_sweep(isf_lattice *lat) {
     uint8_t *a = lat->L.spins, *b = lat->spare;
-    hipError_t e = lat->cur_spare ? launch_sweep_i8_halo(lat->L, lat->tiling, b, a, lat->lists, lat->stream)
-                                  : launch_sweep_i8_halo(lat->L, lat->tiling, a, b, lat->lists, lat->stream);
+    hipError_t e = lat->cur_spare ? launch_sweep_i8_halo(lat->L, lat->tiling, b, a, lat->lists, 1, lat->stream)
+                                  : launch_sweep_i8_halo(lat->L, lat->tiling, a, b, lat->lists, 0, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     lat->cur_spare = !lat->cur_spare;
     return ISF_OK;
 }
 
-// One sweep = four sublattice launches (or one whole-sweep launch) and the
-// one-wave sweep-end launch.
+// One sweep = one whole-sweep launch (its bookkeeping rides in the launch), or
+// four sublattice launches and the one-wave sweep-end launch.
 int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
     const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
     for (uint64_t i = 0; i < n; ++i) {
@@ -268,12 +299,12 @@ int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
             int32_t rc = launch_whole_sweep(lat);
             if (rc)
                 return rc;
-        } else {
-            for (uint32_t s = 0; s < 4; ++s) {
-                int32_t rc = launch_phase(lat, s);
-                if (rc)
-                    return rc;
-            }
+            continue;
+        }
+        for (uint32_t s = 0; s < 4; ++s) {
+            int32_t rc = launch_phase(lat, s);
+            if (rc)
+                return rc;
         }
         int32_t rc = launch_end(lat);
         if (rc)
@@ -318,7 +349,7 @@ int32_t build_graph(isf_lattice *lat) {
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     int32_t rc0;
     if (lat->tiling.kernel == ISF_KERNEL_SWEEP) {
-        if ((rc0 = prepare_spare(lat)))
+        if ((rc0 = prepare_spare(lat)) || (rc0 = prime_whole(lat)))
             return rc0;
         // graphs hold an even number of whole sweeps and start from the main copy
         if (lat->cur_spare && n > 0) {
@@ -501,6 +532,8 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     L.steps = reinterpret_cast<StepDesc *>(lat->aux_dev + al.off_steps);
     L.tables = reinterpret_cast<uint32_t *>(lat->aux_dev + al.off_tables);
     L.records = reinterpret_cast<isf_record *>(lat->aux_dev + al.off_records);
+    L.pos = reinterpret_cast<SweepPos *>(lat->aux_dev + al.off_pos);
+    L.slots2 = reinterpret_cast<Slot *>(lat->aux_dev + al.off_slots2);
     L.X = d->X;
     L.Y = d->Y;
     L.Z = d->Z;
@@ -695,6 +728,8 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
         return rc;
     if ((rc = set_device_of(lat)))
         return rc;
+    if ((rc = flush_whole(lat)))
+        return rc;
     std::vector<StepDesc> sd(n ? n : 1);
     std::vector<uint32_t> tabs((size_t)(n ? n : 1) * kTableWords, 0);
     uint64_t total = 0;
@@ -760,6 +795,8 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n) {
         return fail(ISF_EINVAL, "null output");
     if ((rc = set_device_of(lat)))
         return rc;
+    if ((rc = flush_whole(lat)))
+        return rc;
     if (n)
         HIP_TRY(hipMemcpyAsync(out, lat->L.records, sizeof(isf_record) * n, hipMemcpyDeviceToHost, lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
@@ -794,6 +831,8 @@ int32_t isf_read_observables(isf_lattice *lat, isf_obs *out) {
     if (!out)
         return fail(ISF_EINVAL, "null output");
     if ((rc = set_device_of(lat)))
+        return rc;
+    if ((rc = flush_whole(lat)))
         return rc;
     struct {
         int64_t M, E;
@@ -963,7 +1002,7 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     int32_t status = ISF_OK;
     const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
-    if ((rc = whole ? prepare_spare(lat) : settle(lat))) {
+    if (whole ? ((rc = prepare_spare(lat)) || (rc = prime_whole(lat))) : (rc = settle(lat)) != 0) {
         for (auto &e : ev)
             (void)hipEventDestroy(e);
         return rc;
@@ -975,7 +1014,7 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
             status = whole ? launch_whole_sweep(lat) : launch_phase(lat, s);
             (void)hipEventRecord(ev[8 * i + 2 * s + 1], lat->stream);
         }
-        if (status == ISF_OK)
+        if (status == ISF_OK && !whole)
             status = launch_end(lat);
     }
     double sum[4] = {0, 0, 0, 0};
@@ -1111,7 +1150,7 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
     }
     // batch kernels work on the main copy of the spins
     for (uint32_t i = 0; i < n; ++i)
-        if (lats[i]->cur_spare) {
+        if (lats[i]->cur_spare || lats[i]->whole_active) {
             int32_t rc = settle(lats[i]);
             if (rc)
                 return rc;

@@ -180,7 +180,7 @@ __device__ inline void sweep_end(const LatDev &L) {
 // each) or through returning atomics (a memory round trip before every block
 // can retire).
 template <int NT>
-__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat) {
+__device__ __forceinline__ void finish_block_to(Slot *slots, int dM, int dE, int acc, uint32_t block_in_lat) {
     __shared__ int red[3][NT / 64];
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     dM = wave_sum(dM);
@@ -201,13 +201,18 @@ __device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, in
             sA += red[2][w];
         }
         if (sA) {
-            Slot *slot = &L.slots[block_in_lat % kSlots];
+            Slot *slot = &slots[block_in_lat % kSlots];
             aadd(&slot->dM, sM);
             aadd(&slot->dE, sE);
             aadd(&slot->acc, sA);
         }
     }
     __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat) {
+    finish_block_to<NT>(L.slots, dM, dE, acc, block_in_lat);
 }
 
 // Block-wide sum of four 64-bit values into out[0..3] (256-thread blocks).

@@ -62,6 +62,21 @@ struct StepDesc {
     uint32_t n_discard;
 };
 
+// Schedule position of one sweep of the whole-sweep kernel, double-buffered by
+// sweep parity: the launch of parity q reads pos[q], and its block 0 writes the
+// next sweep's position into pos[1 - q] and folds the previous sweep (whose
+// slots are slots[1 - q]) into M, E, the step's sums and records.
+struct alignas(256) SweepPos {
+    uint64_t t;          // sweep counter of this sweep
+    uint32_t step;       // step of this sweep
+    uint32_t sis;        // sweeps of the step done before this one
+    uint32_t n_sweeps;   // of the step
+    uint32_t n_discard;  // of the step
+    uint32_t run;        // step < n_steps
+    uint32_t pending;    // the slots of this parity hold a sweep not yet folded
+    uint32_t table[kTableWords];
+};
+
 // Everything a kernel needs to work on one film.
 struct LatDev {
     uint8_t *spins;       // INT8: [Z+2][Y][W] bytes; BITPACK: [Z+2][Y][2][W/32] words
@@ -82,11 +97,14 @@ struct LatDev {
     uint32_t n_items[4];
     uint32_t items_off[4];
     uint32_t ybits, dbits;
+    // whole-sweep kernel: positions of the two sweep parities and the slots of parity 1
+    SweepPos *pos;
+    Slot *slots2;
 };
 
 // Aux buffer layout.
 struct AuxLayout {
-    uint64_t off_state, off_slots, off_steps, off_tables, off_records, total;
+    uint64_t off_state, off_slots, off_steps, off_tables, off_records, off_pos, off_slots2, total;
 };
 
 inline AuxLayout aux_layout(uint32_t max_steps) {
@@ -99,7 +117,9 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
     a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 4096);
     a.off_tables = up(a.off_steps + sizeof(StepDesc) * max_steps, 256);
     a.off_records = up(a.off_tables + sizeof(uint32_t) * kTableWords * max_steps, 256);
-    a.total = up(a.off_records + sizeof(isf_record) * max_steps, 256);
+    a.off_pos = up(a.off_records + sizeof(isf_record) * max_steps, 4096);
+    a.off_slots2 = up(a.off_pos + 2 * sizeof(SweepPos), 4096);
+    a.total = up(a.off_slots2 + sizeof(Slot) * kSlots, 256);
     return a;
 }
 

@@ -38,6 +38,16 @@
 //   * two entries per iteration keep two gathers in flight.
 // HBM traffic per sweep: each block reads (TXD + 2 HX)(TYR + 2 HY) dwords per
 // plane plus its lists and writes its tile's occupied dwords.
+//
+// Per-sweep bookkeeping needs no launch of its own: the schedule position
+// (sweep counter, step, threshold table) is double-buffered by sweep parity.
+// The launch of parity q reads pos[q]; wave 0 of its block 0 folds the
+// previous sweep's slot sums (parity 1 - q, complete since that launch ended)
+// into M, E, the step's sums and its record, and writes the next sweep's
+// position into pos[1 - q].  Its loads are issued when the block starts and
+// used when its tile is done, so the fold adds no latency in between.  After
+// the last sweep of a run, one small launch (k_whole_flush) folds that sweep
+// and hands the position back to the film state read by every other path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -104,7 +114,168 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t per_xcd) 
     return (b & 7u) * per_xcd + (b >> 3);
 }
 
+__device__ __forceinline__ Slot *slots_of(const LatDev &L, uint32_t parity) { return parity ? L.slots2 : L.slots; }
+
+// Loads of the per-sweep bookkeeping, issued early (wave 0 of block 0).
+struct Book {
+    int64_t sdM, sdE, sacc;  // this lane's slot of the previous sweep
+    // lane 0: the previous sweep's position, this sweep's position, the film state
+    uint32_t p_pending, p_run, p_step, p_sis, p_ns, p_nd;
+    uint64_t c_t;
+    uint32_t c_step, c_sis, c_ns, c_nd, c_run, n_steps;
+    int64_t M, E, sM, sA, sE, sC;
+};
+
+__device__ __forceinline__ Book book_load(const LatDev &L, uint32_t prev, uint32_t cur, uint32_t lane) {
+    Book k;
+    const Slot *ps = slots_of(L, prev);
+    k.sdM = ps[lane].dM;  // kSlots == 64: one slot per lane
+    k.sdE = ps[lane].dE;
+    k.sacc = ps[lane].acc;
+    k.p_pending = k.p_run = k.p_step = k.p_sis = k.p_ns = k.p_nd = 0;
+    k.c_t = 0;
+    k.c_step = k.c_sis = k.c_ns = k.c_nd = k.c_run = k.n_steps = 0;
+    k.M = k.E = k.sM = k.sA = k.sE = k.sC = 0;
+    if (lane == 0) {
+        const SweepPos &pp = L.pos[prev], &cp = L.pos[cur];
+        k.p_pending = pp.pending;
+        k.p_run = pp.run;
+        k.p_step = pp.step;
+        k.p_sis = pp.sis;
+        k.p_ns = pp.n_sweeps;
+        k.p_nd = pp.n_discard;
+        k.c_t = cp.t;
+        k.c_step = cp.step;
+        k.c_sis = cp.sis;
+        k.c_ns = cp.n_sweeps;
+        k.c_nd = cp.n_discard;
+        k.c_run = cp.run;
+        const DevState *st = L.st;
+        k.n_steps = st->n_steps;
+        k.M = st->M;
+        k.E = st->E;
+        k.sM = st->sum_M;
+        k.sA = st->sum_absM;
+        k.sE = st->sum_E;
+        k.sC = st->accepted;
+    }
+    return k;
+}
+
+// Fold the previous sweep (parity prev) into M, E, the step's sums and, if it
+// ended its step, the step's record; clear its slots.  One wave.
+__device__ __forceinline__ void book_fold(const LatDev &L, uint32_t prev, const Book &k, uint32_t lane) {
+    const int64_t dM = wave_sum(k.sdM), dE = wave_sum(k.sdE), acc = wave_sum(k.sacc);
+    Slot *ps = slots_of(L, prev);
+    ps[lane].dM = 0;
+    ps[lane].dE = 0;
+    ps[lane].acc = 0;
+    if (lane == 0 && k.p_pending) {
+        DevState *st = L.st;
+        const int64_t M = k.M + dM, E = k.E + dE;
+        st->M = M;
+        st->E = E;
+        if (k.p_run) {
+            int64_t sM = k.sM, sA = k.sA, sE = k.sE, sC = k.sC;
+            if (k.p_sis >= k.p_nd) {
+                sM += M;
+                sA += M < 0 ? -M : M;
+                sE += E;
+                sC += acc;
+            }
+            if (k.p_sis + 1 >= k.p_ns) {
+                isf_record *rec = &L.records[k.p_step];
+                rec->M = M;
+                rec->E = E;
+                rec->sum_M = sM;
+                rec->sum_absM = sA;
+                rec->sum_E = sE;
+                rec->accepted = sC;
+                sM = sA = sE = sC = 0;
+            }
+            st->sum_M = sM;
+            st->sum_absM = sA;
+            st->sum_E = sE;
+            st->accepted = sC;
+        }
+        L.pos[prev].pending = 0;
+    }
+}
+
+// Write the position of the sweep after the current one (parity cur) into
+// pos[1 - cur]; tab holds the current sweep's thresholds.  One wave.
+__device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, const Book &k, const uint32_t *tab,
+                                             uint32_t lane) {
+    uint32_t next_step = 0xFFFFFFFFu;
+    if (lane == 0) {
+        uint32_t step = k.c_step, sis = k.c_sis, ns = k.c_ns, nd = k.c_nd, run = k.c_run;
+        if (run) {
+            if (++sis >= ns) {
+                ++step;
+                sis = 0;
+                run = step < k.n_steps;
+                if (run) {
+                    ns = L.steps[step].n_sweeps;
+                    nd = L.steps[step].n_discard;
+                    next_step = step;
+                }
+            }
+        }
+        SweepPos &np = L.pos[1 - cur];
+        np.t = k.c_t + 1;
+        np.step = step;
+        np.sis = sis;
+        np.n_sweeps = ns;
+        np.n_discard = nd;
+        np.run = run;
+        np.pending = 0;
+        L.pos[cur].pending = 1;  // this sweep's slots wait for the next fold
+    }
+    next_step = __shfl(next_step, 0, 64);
+    if (lane < kTableWords)
+        L.pos[1 - cur].table[lane] =
+            next_step != 0xFFFFFFFFu ? L.tables[(size_t)next_step * kTableWords + lane] : tab[lane];
+}
+
 }  // namespace
+
+// Start of a run of whole-sweep launches: the position of the first sweep
+// (parity q) from the film state; nothing is pending.  One wave.
+__global__ __launch_bounds__(64) void k_whole_prime(LatDev L, uint32_t q) {
+    const uint32_t lane = threadIdx.x;
+    const DevState *st = L.st;
+    if (lane == 0) {
+        SweepPos &p = L.pos[q];
+        const uint32_t step = st->step;
+        p.t = st->t;
+        p.step = step;
+        p.sis = st->sweep_in_step;
+        p.run = step < st->n_steps;
+        p.n_sweeps = p.run ? L.steps[step].n_sweeps : 0u;
+        p.n_discard = p.run ? L.steps[step].n_discard : 0u;
+        p.pending = 0;
+        L.pos[1 - q].pending = 0;
+    }
+    if (lane < kTableWords)
+        L.pos[q].table[lane] = st->cur_table[lane];
+}
+
+// End of a run: fold the last sweep (parity q_last) and make the position
+// after it the film state's.  One wave.
+__global__ __launch_bounds__(64) void k_whole_flush(LatDev L, uint32_t q_last) {
+    const uint32_t lane = threadIdx.x;
+    const Book k = book_load(L, q_last, 1 - q_last, lane);
+    book_fold(L, q_last, k, lane);
+    const SweepPos &n = L.pos[1 - q_last];
+    DevState *st = L.st;
+    if (lane == 0) {
+        st->t = n.t;
+        st->step = n.step;
+        st->sweep_in_step = n.sis;
+    }
+    if (lane < kTableWords)
+        st->cur_table[lane] = n.table[lane];
+}
 
 // Lists of occupied dwords per phase for every tile (run once per film and
 // tiling; occupancy never changes).  One block per tile; the order of entries
@@ -166,7 +337,7 @@ __global__ __launch_bounds__(256) void k_sweep_lists(LatDev L, uint32_t nbx, uin
 template <int TXD, int TYR, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *__restrict__ src,
                                                       uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
-                                                      uint32_t nbx, uint32_t per_xcd) {
+                                                      uint32_t nbx, uint32_t per_xcd, uint32_t q) {
     using G = Geo<TXD, TYR>;
     constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL;
     extern __shared__ __align__(16) uint8_t smb[];
@@ -191,12 +362,17 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
     const uint32_t d0 = bx * TXD, y0 = by * TYR;
     const uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
     const uint4 cnt = *reinterpret_cast<const uint4 *>(rec);  // uniform: a scalar load
+    const bool booker = b == 0 && tid < 64;                   // wave 0 of block 0 keeps the books
+    Book bk;
+    if (booker)
+        bk = book_load(L, 1 - q, q, tid);
 
+    const SweepPos &P = L.pos[q];
     if (tid < kTableWords)
-        tab[tid] = L.st->cur_table[tid];
+        tab[tid] = P.table[tid];
     if (tid == 0) {
-        t_sh = (uint32_t)L.st->t;
-        run_sh = L.st->step < L.st->n_steps;
+        t_sh = (uint32_t)P.t;
+        run_sh = P.run;
     }
     const uint32_t ynd = Y * nd;
     for (uint32_t i = tid; i < np * RYN + RX; i += NT) {
@@ -282,8 +458,13 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
         R[(np - 1) * PL + i] = kVacant;
     }
     __syncthreads();
-    if (!run_sh)
-        return;  // uniform: the schedule is finished
+    if (!run_sh) {  // uniform: the schedule is finished; the sweep still counts
+        if (booker) {
+            book_fold(L, 1 - q, bk, tid);
+            book_advance(L, q, bk, tab, tid);
+        }
+        return;
+    }
 
     int dM = 0, dE = 0, acc = 0;
     const uint32_t t = t_sh;
@@ -388,7 +569,11 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
                 *reinterpret_cast<uint32_t *>(out + p * planeb + (ym & 0x7FFFFFFFu) * rowb + (dm & 0x7FFFFFFFu) * 4u) = v;
         }
     }
-    finish_block<NT>(L, dM, dE, acc, b);
+    finish_block_to<NT>(slots_of(L, q), dM, dE, acc, b);
+    if (booker) {
+        book_fold(L, 1 - q, bk, tid);
+        book_advance(L, q, bk, tab, tid);
+    }
 }
 
 namespace {
@@ -402,20 +587,20 @@ void grid_of(const LatDev &L, uint32_t &nbx, uint32_t &per_xcd, uint32_t &tiles)
 
 template <int TXD, int TYR>
 hipError_t launch_halo_t(const LatDev &L, const uint8_t *src, uint8_t *dst, const uint8_t *lists, uint32_t nt,
-                         hipStream_t s) {
+                         uint32_t q, hipStream_t s) {
     uint32_t nbx, per_xcd, tiles;
     grid_of<TXD, TYR>(L, nbx, per_xcd, tiles);
     const size_t lds = Geo<TXD, TYR>::lds_bytes(L.Z);
     const dim3 grid(per_xcd * 8);
     if (nt == 1024)
         hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 1024>), grid, dim3(1024), lds, s, L, src, dst, lists, nbx,
-                           per_xcd);
+                           per_xcd, q);
     else if (nt == 512)
         hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 512>), grid, dim3(512), lds, s, L, src, dst, lists, nbx,
-                           per_xcd);
+                           per_xcd, q);
     else
         hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 256>), grid, dim3(256), lds, s, L, src, dst, lists, nbx,
-                           per_xcd);
+                           per_xcd, q);
     return hipGetLastError();
 }
 
@@ -484,18 +669,29 @@ hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists,
     return hipErrorInvalidValue;
 }
 
-// One sweep reading the film from src and writing it to dst (both laid out
-// like the spin buffer; dst must already hold the film's vacancies), with the
-// lists built for the same tiling.
+// One sweep of parity q reading the film from src and writing it to dst (both
+// laid out like the spin buffer; dst must already hold the film's vacancies),
+// with the lists built for the same tiling; a run of such sweeps starts with
+// launch_whole_prime and ends with launch_whole_flush.
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
-                                const uint8_t *lists, hipStream_t s) {
+                                const uint8_t *lists, uint32_t q, hipStream_t s) {
     const uint32_t nt = 64u * tl.ry;  // 4, 8 or 16 waves
 #define ISF_CASE(A, B) \
     if (tl.tx == A && tl.ty == B) \
-        return launch_halo_t<A, B>(L, src, dst, lists, nt, s);
+        return launch_halo_t<A, B>(L, src, dst, lists, nt, q, s);
     ISF_HALO_SHAPES(ISF_CASE)
 #undef ISF_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s) {
+    hipLaunchKernelGGL(k_whole_prime, dim3(1), dim3(64), 0, s, L, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s) {
+    hipLaunchKernelGGL(k_whole_flush, dim3(1), dim3(64), 0, s, L, q_last);
+    return hipGetLastError();
 }
 
 }  // namespace isf

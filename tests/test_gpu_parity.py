@@ -421,3 +421,28 @@ def test_sweep_kernel_equals_tiles_tscan_film(isf):
     assert n == 6 and ms[0] > 0.0
     np.testing.assert_array_equal(a.records(), b.records())
     np.testing.assert_array_equal(a.spins(), b.spins())
+
+
+def test_sweep_kernel_switches_and_reads_midway(isf):
+    """Whole-sweep runs opened and closed at odd places: chunked advances, kernel
+    switches inside a step, observables and spins read between chunks."""
+    h = _rand_h((46, 328), 6, 99)
+    steps = [(2.5, 30, 7, 2), (0.8, -45, 5, 1), (6.0, 5, 9, 3)]
+    g, o = _pair(isf, h, 6, 4242, replica=2, init=2)
+    g.set_tuning(32, 16, 8, False, 2)
+    g.schedule_load(steps)
+    _say("sweep kernel switching")
+    done = 0
+    for chunk, kernel in ((3, 2), (1, 2), (4, 0), (2, 2), (5, 2), (3, 0), (1, 2), (2, 2)):
+        if kernel == 2:
+            g.set_tuning(32, 16, 8, False, 2)
+        else:
+            g.set_tuning(64, 4, 2, False, 0)
+        done += g.advance(chunk)
+        assert g.observables()["sweeps"] == done
+        if chunk == 4:
+            g.spins()  # brings the spins back from the spare copy mid-run
+    g.advance(100)
+    ro = np.array([o.run(*s).as_tuple() for s in steps])
+    np.testing.assert_array_equal(g.records(), ro)
+    _assert_same(g, o)
