@@ -116,75 +116,77 @@ __device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t per_xcd) 
 
 __device__ __forceinline__ Slot *slots_of(const LatDev &L, uint32_t parity) { return parity ? L.slots2 : L.slots; }
 
-// Loads of the per-sweep bookkeeping, issued early (wave 0 of block 0).
-struct Book {
-    int64_t sdM, sdE, sacc;  // this lane's slot of the previous sweep
-    // lane 0: the previous sweep's position, this sweep's position, the film state
-    uint32_t p_pending, p_run, p_step, p_sis, p_ns, p_nd;
-    uint64_t c_t;
-    uint32_t c_step, c_sis, c_ns, c_nd, c_run, n_steps;
-    int64_t M, E, sM, sA, sE, sC;
+// The per-sweep bookkeeping's inputs, staged in LDS by wave 0 of block 0:
+// the previous sweep's position (words 0-7), this sweep's position (8-15),
+// the film state's first 18 words (16-33: M, E, t, step, sweep_in_step, the
+// step's sums, n_steps) and the previous sweep's 64 slots.  The loads are
+// issued before the block's region loads and stored once those have landed,
+// so they add neither latency nor live registers to the sweep.
+constexpr int kBookWords = 34;
+struct BookLds {
+    uint32_t w[kBookWords];
+    int64_t dM[kSlots], dE[kSlots], acc[kSlots];
+};
+static_assert(offsetof(SweepPos, pending) == 28 && offsetof(SweepPos, t) == 0, "position words");
+static_assert(offsetof(DevState, M) == 0 && offsetof(DevState, sum_M) == 32 && offsetof(DevState, accepted) == 56 &&
+                  offsetof(DevState, n_steps) == 68,
+              "film state words");
+
+struct BookRegs {
+    uint32_t w;
+    int64_t dM, dE, acc;
 };
 
-__device__ __forceinline__ Book book_load(const LatDev &L, uint32_t prev, uint32_t cur, uint32_t lane) {
-    Book k;
-    const Slot *ps = slots_of(L, prev);
-    k.sdM = ps[lane].dM;  // kSlots == 64: one slot per lane
-    k.sdE = ps[lane].dE;
-    k.sacc = ps[lane].acc;
-    k.p_pending = k.p_run = k.p_step = k.p_sis = k.p_ns = k.p_nd = 0;
-    k.c_t = 0;
-    k.c_step = k.c_sis = k.c_ns = k.c_nd = k.c_run = k.n_steps = 0;
-    k.M = k.E = k.sM = k.sA = k.sE = k.sC = 0;
-    if (lane == 0) {
-        const SweepPos &pp = L.pos[prev], &cp = L.pos[cur];
-        k.p_pending = pp.pending;
-        k.p_run = pp.run;
-        k.p_step = pp.step;
-        k.p_sis = pp.sis;
-        k.p_ns = pp.n_sweeps;
-        k.p_nd = pp.n_discard;
-        k.c_t = cp.t;
-        k.c_step = cp.step;
-        k.c_sis = cp.sis;
-        k.c_ns = cp.n_sweeps;
-        k.c_nd = cp.n_discard;
-        k.c_run = cp.run;
-        const DevState *st = L.st;
-        k.n_steps = st->n_steps;
-        k.M = st->M;
-        k.E = st->E;
-        k.sM = st->sum_M;
-        k.sA = st->sum_absM;
-        k.sE = st->sum_E;
-        k.sC = st->accepted;
-    }
-    return k;
+__device__ __forceinline__ BookRegs book_issue(const LatDev &L, uint32_t prev, uint32_t cur, uint32_t lane) {
+    BookRegs r;
+    const uint32_t *src = lane < 8    ? reinterpret_cast<const uint32_t *>(&L.pos[prev]) + lane
+                          : lane < 16 ? reinterpret_cast<const uint32_t *>(&L.pos[cur]) + (lane - 8)
+                                      : reinterpret_cast<const uint32_t *>(L.st) + (lane - 16);
+    r.w = lane < (uint32_t)kBookWords ? *src : 0u;
+    const Slot &sl = slots_of(L, prev)[lane];  // kSlots == 64: one slot per lane
+    r.dM = sl.dM;
+    r.dE = sl.dE;
+    r.acc = sl.acc;
+    return r;
+}
+
+__device__ __forceinline__ void book_stage(BookLds &bk, const BookRegs &r, uint32_t lane) {
+    if (lane < (uint32_t)kBookWords)
+        bk.w[lane] = r.w;
+    bk.dM[lane] = r.dM;
+    bk.dE[lane] = r.dE;
+    bk.acc[lane] = r.acc;
+}
+
+__device__ __forceinline__ int64_t w64(const BookLds &bk, int i) {
+    return (int64_t)((uint64_t)bk.w[i] | ((uint64_t)bk.w[i + 1] << 32));
 }
 
 // Fold the previous sweep (parity prev) into M, E, the step's sums and, if it
 // ended its step, the step's record; clear its slots.  One wave.
-__device__ __forceinline__ void book_fold(const LatDev &L, uint32_t prev, const Book &k, uint32_t lane) {
-    const int64_t dM = wave_sum(k.sdM), dE = wave_sum(k.sdE), acc = wave_sum(k.sacc);
+__device__ __forceinline__ void book_fold(const LatDev &L, uint32_t prev, const BookLds &bk, uint32_t lane) {
+    const int64_t dM = wave_sum(bk.dM[lane]), dE = wave_sum(bk.dE[lane]), acc = wave_sum(bk.acc[lane]);
     Slot *ps = slots_of(L, prev);
     ps[lane].dM = 0;
     ps[lane].dE = 0;
     ps[lane].acc = 0;
-    if (lane == 0 && k.p_pending) {
+    const uint32_t p_step = bk.w[2], p_sis = bk.w[3], p_ns = bk.w[4], p_nd = bk.w[5], p_run = bk.w[6];
+    const uint32_t p_pending = bk.w[7];
+    if (lane == 0 && p_pending) {
         DevState *st = L.st;
-        const int64_t M = k.M + dM, E = k.E + dE;
+        const int64_t M = w64(bk, 16) + dM, E = w64(bk, 18) + dE;
         st->M = M;
         st->E = E;
-        if (k.p_run) {
-            int64_t sM = k.sM, sA = k.sA, sE = k.sE, sC = k.sC;
-            if (k.p_sis >= k.p_nd) {
+        if (p_run) {
+            int64_t sM = w64(bk, 24), sA = w64(bk, 26), sE = w64(bk, 28), sC = w64(bk, 30);
+            if (p_sis >= p_nd) {
                 sM += M;
                 sA += M < 0 ? -M : M;
                 sE += E;
                 sC += acc;
             }
-            if (k.p_sis + 1 >= k.p_ns) {
-                isf_record *rec = &L.records[k.p_step];
+            if (p_sis + 1 >= p_ns) {
+                isf_record *rec = &L.records[p_step];
                 rec->M = M;
                 rec->E = E;
                 rec->sum_M = sM;
@@ -204,16 +206,17 @@ __device__ __forceinline__ void book_fold(const LatDev &L, uint32_t prev, const 
 
 // Write the position of the sweep after the current one (parity cur) into
 // pos[1 - cur]; tab holds the current sweep's thresholds.  One wave.
-__device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, const Book &k, const uint32_t *tab,
+__device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, const BookLds &bk, const uint32_t *tab,
                                              uint32_t lane) {
     uint32_t next_step = 0xFFFFFFFFu;
     if (lane == 0) {
-        uint32_t step = k.c_step, sis = k.c_sis, ns = k.c_ns, nd = k.c_nd, run = k.c_run;
+        uint32_t step = bk.w[10], sis = bk.w[11], ns = bk.w[12], nd = bk.w[13], run = bk.w[14];
+        const uint32_t n_steps = bk.w[33];
         if (run) {
             if (++sis >= ns) {
                 ++step;
                 sis = 0;
-                run = step < k.n_steps;
+                run = step < n_steps;
                 if (run) {
                     ns = L.steps[step].n_sweeps;
                     nd = L.steps[step].n_discard;
@@ -222,7 +225,7 @@ __device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, cons
             }
         }
         SweepPos &np = L.pos[1 - cur];
-        np.t = k.c_t + 1;
+        np.t = (uint64_t)w64(bk, 8) + 1;
         np.step = step;
         np.sis = sis;
         np.n_sweeps = ns;
@@ -263,9 +266,10 @@ __global__ __launch_bounds__(64) void k_whole_prime(LatDev L, uint32_t q) {
 // End of a run: fold the last sweep (parity q_last) and make the position
 // after it the film state's.  One wave.
 __global__ __launch_bounds__(64) void k_whole_flush(LatDev L, uint32_t q_last) {
+    __shared__ BookLds bk;
     const uint32_t lane = threadIdx.x;
-    const Book k = book_load(L, q_last, 1 - q_last, lane);
-    book_fold(L, q_last, k, lane);
+    book_stage(bk, book_issue(L, q_last, 1 - q_last, lane), lane);
+    book_fold(L, q_last, bk, lane);
     const SweepPos &n = L.pos[1 - q_last];
     DevState *st = L.st;
     if (lane == 0) {
@@ -363,9 +367,10 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
     const uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
     const uint4 cnt = *reinterpret_cast<const uint4 *>(rec);  // uniform: a scalar load
     const bool booker = b == 0 && tid < 64;                   // wave 0 of block 0 keeps the books
-    Book bk;
+    __shared__ BookLds bk;
+    BookRegs br;
     if (booker)
-        bk = book_load(L, 1 - q, q, tid);
+        br = book_issue(L, 1 - q, q, tid);
 
     const SweepPos &P = L.pos[q];
     if (tid < kTableWords)
@@ -392,35 +397,43 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
         }
     }
 
-    // This block's lists, HBM -> LDS (8-byte words; each list is 8-byte aligned).
-    {
-        const uint32_t c4[4] = {cnt.x, cnt.y, cnt.z, cnt.w};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint32_t nw = (c4[s] + 3u) / 4u;
-            const uint2 *from = reinterpret_cast<const uint2 *>(rec + 16 + 2u * G::list_off(s, Z));
-            uint2 *to = reinterpret_cast<uint2 *>(lst + G::list_off(s, Z));
-            for (uint32_t i = tid; i < nw; i += NT)
-                to[i] = from[i];
-        }
-    }
-
-    // The region: planes 1..Z from the film, the padding planes are vacancies.
-    // Films at least as large as the region, with an even number of dwords per
-    // row, take 8-byte loads (dword pairs never straddle the periodic seam and
-    // stay 8-byte aligned) with the wrap done arithmetically, eight loads in
-    // flight per thread; other films take 4-byte loads with the wrap by modulo.
+    // The region and this block's lists, HBM -> LDS.  Planes 1..Z come from the
+    // film, the padding planes are vacancies; the lists are 8-byte words (4
+    // entries) of the four per-phase lists, each 8-byte aligned.  Films at
+    // least as large as the region, with an even number of dwords per row, take
+    // 8-byte region loads (dword pairs never straddle the periodic seam and stay
+    // 8-byte aligned) with the wrap done arithmetically; every load of a batch
+    // (KB region pairs and KL list words per thread, one batch for films of up
+    // to 8 planes) is issued before the first one is stored, so the load phase
+    // costs about one memory round trip.  Other films take 4-byte region loads
+    // with the wrap by modulo.
     const uint32_t rowb = nd * 4u;
     const size_t planeb = (size_t)Y * rowb;
     const char *base = reinterpret_cast<const char *>(src);
     const bool wide = (nd & 1u) == 0 && nd >= (uint32_t)RX && Y >= (uint32_t)RYN;  // uniform
-    if (wide) {
+    const uint32_t w0 = (cnt.x + 3u) / 4u, w1 = (cnt.y + 3u) / 4u, w2 = (cnt.z + 3u) / 4u, w3 = (cnt.w + 3u) / 4u;
+    const uint32_t e1 = w0, e2 = e1 + w1, e3 = e2 + w2, nwl = e3 + w3;  // list word boundaries
+    const uint2 *lsrc = reinterpret_cast<const uint2 *>(rec + 16);
+    uint2 *ldst = reinterpret_cast<uint2 *>(lst);
+    // flat list word i -> word offset of its list's slot (lists start at list_off(s) / 4 words)
+    auto list_word = [&](uint32_t i) -> uint32_t {
+        if (i < e1)
+            return i;
+        if (i < e2)
+            return G::list_off(1, Z) / 4u + (i - e1);
+        if (i < e3)
+            return G::list_off(2, Z) / 4u + (i - e2);
+        return G::list_off(3, Z) / 4u + (i - e3);
+    };
+    if (wide && Z * planeb < (1ull << 32)) {  // byte offsets within the film fit 32 bits
+        const uint32_t planeb32 = (uint32_t)planeb;
         constexpr uint32_t RX2 = RX / 2, PL2 = PL / 2;
+        constexpr int KB = NT >= 1024 ? 6 : 12, KL = NT >= 1024 ? 1 : 2;
         const uint32_t n = Z * PL2;
-        for (uint32_t i0 = 0; i0 < n; i0 += 8 * NT) {
-            uint2 v[8];
+        for (uint32_t i0 = 0, l0 = 0; i0 < n || l0 < nwl; i0 += KB * NT, l0 += KL * NT) {
+            uint2 v[KB], lv[KL];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < KB; ++k) {
                 const uint32_t i = i0 + k * NT + tid;
                 if (i < n) {
                     const uint32_t p = i / PL2 + 1, r = i % PL2;
@@ -430,19 +443,33 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
                     y -= y >= (int)Y ? (int)Y : 0;
                     d += d < 0 ? (int)nd : 0;
                     d -= d >= (int)nd ? (int)nd : 0;
-                    v[k] = *reinterpret_cast<const uint2 *>(base + p * planeb + (uint32_t)y * rowb + (uint32_t)d * 4u);
+                    v[k] = *reinterpret_cast<const uint2 *>(base + (p * planeb32 + (uint32_t)y * rowb + (uint32_t)d * 4u));
                 }
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < KL; ++k) {
+                const uint32_t i = l0 + k * NT + tid;
+                if (i < nwl)
+                    lv[k] = lsrc[list_word(i)];
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
                 const uint32_t i = i0 + k * NT + tid;
                 if (i < n) {
                     const uint32_t p = i / PL2 + 1, r = i % PL2;
                     *reinterpret_cast<uint2 *>(&R[p * PL + 2 * r]) = v[k];
                 }
             }
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                const uint32_t i = l0 + k * NT + tid;
+                if (i < nwl)
+                    ldst[list_word(i)] = lv[k];
+            }
         }
     } else {
+        for (uint32_t i = tid; i < nwl; i += NT)
+            ldst[list_word(i)] = lsrc[list_word(i)];
         const uint32_t n = Z * PL;
 #pragma unroll 4
         for (uint32_t i = tid; i < n; i += NT) {
@@ -457,6 +484,8 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
         R[i] = kVacant;
         R[(np - 1) * PL + i] = kVacant;
     }
+    if (booker)
+        book_stage(bk, br, tid);
     __syncthreads();
     if (!run_sh) {  // uniform: the schedule is finished; the sweep still counts
         if (booker) {
