@@ -142,13 +142,13 @@ def bench_batched(args):
         return [Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
 
     t0 = time.perf_counter()
-    tuned = tune_batch(make, lambda i: sched[i], 0, sweeps=6,
-                       candidates=[(64, 4, 1), (64, 4, 2), (32, 8, 2), (16, 16, 2)])
+    tuned = tune_batch(make, lambda i: sched[i], 0, sweeps=6)
     log("batch tuning %.1fs: best %s mode %d (%.3f ms/sweep)" % (time.perf_counter() - t0, tuned["tiling"],
                                                                  tuned["mode"], tuned["ms_per_sweep"]))
+    kernel = KERNEL_SWEEP if tuned["mode"] == 2 else 0
     lats = make()
     for l in lats:
-        l.set_tuning(*tuned["tiling"], False)
+        l.set_tuning(*tuned["tiling"], False, kernel)
     n_occ = [l.observables()["n_occ"] for l in lats]
     b = Batch(len(lats), stream=stream)
     torch.cuda.synchronize()
@@ -158,7 +158,7 @@ def bench_batched(args):
     attempts = sum(n * len(hnums) * spst for n in n_occ)
     out = {"value": round(attempts / dt, 1), "unit": "spin-flip attempts/s", "replicas": len(reps),
            "sweeps_per_replica": len(hnums) * spst, "attempts": attempts, "seconds": round(dt, 4),
-           "mode": "persistent" if tuned["mode"] == 1 else "phase_launch", "tiling": tuned["tiling"],
+           "mode": {0: "phase_launch", 1: "persistent", 2: "whole_sweep"}[tuned["mode"]], "tiling": tuned["tiling"],
            "tuning": tuned["all"]}
     # the same replicas one after another through the plain path (a sample, shortened schedule)
     sample = list(range(0, len(reps), 16))
@@ -168,7 +168,7 @@ def bench_batched(args):
     for i in sample:
         r = reps[i]
         l = Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream)
-        l.set_tuning(*tuned["tiling"], True)
+        l.set_tuning(*tuned["tiling"], True, kernel)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         l.run_schedule(sched[i][:short])
@@ -213,7 +213,7 @@ def bench_serving(args, reqs, hmap):
     s = stats.summary()
     s["wall_s"] = round(wall, 2)
     s["offered_attempts_per_s"] = round(s["attempts"] / args.serve_duration, 1)
-    s["mode"] = "persistent" if args.serve_mode == 1 else "phase_launch"
+    s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep"}[args.serve_mode]
     s["arrivals"] = "Poisson 50 req/s for %g s" % args.serve_duration
     return s
 

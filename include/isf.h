@@ -218,7 +218,12 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
  * ISF_BATCH_PHASE_LAUNCH mode one kernel launch per sublattice covers every
  * lattice; in ISF_BATCH_PERSISTENT mode one cooperative launch runs a whole
  * chunk of sweeps for all lattices, with a grid-wide barrier between
- * sublattices.  Each lattice's trajectory is identical to running it alone.
+ * sublattices; in ISF_BATCH_WHOLE mode (INT8 lattices) one launch per sweep
+ * runs the whole sweep of every lattice with the whole-sweep kernel
+ * (ISF_KERNEL_SWEEP), in the shape of lats[0]'s tuning if it selects that
+ * kernel, else 16 x 16 with 4 waves (EINVAL if that shape's LDS does not fit
+ * the deepest film).  Each lattice's trajectory is identical to running it
+ * alone.
  *
  * A batch context owns a pinned host staging area for its launch table and
  * uses the caller's device workspace (isf_batch_workspace_bytes) for the
@@ -226,7 +231,7 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
  * and be idle on their own streams; the batch's work runs on the batch
  * stream.  isf_batch_advance advances every lattice by min(max_sweeps, its
  * remaining sweeps) and returns without waiting; isf_batch_sync waits. */
-enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1 };
+enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1, ISF_BATCH_WHOLE = 2 };
 
 typedef struct isf_batch isf_batch;
 

@@ -19,8 +19,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST, KERNEL_SWEEP,
-                   KERNEL_TILES, IsfError)
+from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, BATCH_WHOLE, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST,
+                   KERNEL_SWEEP, KERNEL_TILES, IsfError)
 
 TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
@@ -144,40 +144,44 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
             "ms_per_sweep": best["ms_per_sweep"], "all": timings}
 
 
+BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH), (16, 16, 4, BATCH_WHOLE),
+                    (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE)]
+
+
 def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list], fmt: int,
-               sweeps: int = 8, candidates: Optional[Sequence[Tuple[int, int, int]]] = None,
-               modes: Sequence[int] = (BATCH_PHASE_LAUNCH, BATCH_PERSISTENT)) -> dict:
-    """Time launch shapes and batch modes on a batch of films (fresh copies per candidate)."""
+               sweeps: int = 8, candidates: Optional[Sequence[Tuple[int, int, int, int]]] = None) -> dict:
+    """Time (tile_x, tile_y, rows_or_waves, batch mode) candidates on a batch of films
+    (fresh copies per candidate); whole-sweep candidates apply to INT8 films only."""
     import torch
 
     from .lattice import Batch
 
-    cands = list(candidates or TILINGS[fmt])
+    cands = [c for c in (candidates or BATCH_CANDIDATES) if fmt == FORMAT_INT8 or c[3] != BATCH_WHOLE]
     timings = []
     ref = None
-    for tl in cands:
-        for mode in modes:
-            lats = make_lats()
-            for i, l in enumerate(lats):
-                l.set_tuning(tl[0], tl[1], tl[2], False)
-                l.schedule_load(schedule_of(i))
-            b = Batch(len(lats))
-            b.advance(lats, 2, mode)  # warm-up sweeps
-            b.sync()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            b.advance(lats, sweeps, mode)
-            b.sync()
-            dt = time.perf_counter() - t0
-            state = [l.observables() for l in lats]
-            key = [(s["M"], s["E"], s["sweeps"]) for s in state]
-            if ref is None:
-                ref = key
-            elif key != ref:
-                raise AssertionError("batch shape %s mode %d changed the trajectory" % (tl, mode))
-            timings.append({"tiling": list(tl), "mode": mode, "ms_per_sweep": dt * 1e3 / sweeps})
-            b.close()
-            for l in lats:
-                l.close()
+    for tx, ty, r, mode in cands:
+        lats = make_lats()
+        kernel = KERNEL_SWEEP if mode == BATCH_WHOLE else KERNEL_TILES
+        for i, l in enumerate(lats):
+            l.set_tuning(tx, ty, r, False, kernel)
+            l.schedule_load(schedule_of(i))
+        b = Batch(len(lats))
+        b.advance(lats, 2, mode)  # warm-up sweeps
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.advance(lats, sweeps, mode)
+        b.sync()
+        dt = time.perf_counter() - t0
+        state = [l.observables() for l in lats]
+        key = [(s["M"], s["E"], s["sweeps"]) for s in state]
+        if ref is None:
+            ref = key
+        elif key != ref:
+            raise AssertionError("batch shape %s mode %d changed the trajectory" % ((tx, ty, r), mode))
+        timings.append({"tiling": [tx, ty, r], "mode": mode, "ms_per_sweep": dt * 1e3 / sweeps})
+        b.close()
+        for l in lats:
+            l.close()
     best = min(timings, key=lambda r: r["ms_per_sweep"])
     return {"tiling": best["tiling"], "mode": best["mode"], "ms_per_sweep": best["ms_per_sweep"], "all": timings}

@@ -30,6 +30,9 @@ hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 const uint8_t *lists, uint32_t q, hipStream_t s);
 hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
+hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *begins, uint32_t n_ents,
+                                      uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s);
+uint32_t halo_tiles(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t &nbx);
 hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s);
 hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
 uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
@@ -192,7 +195,7 @@ struct isf_batch {
     uint8_t *ws_dev;
     uint64_t ws_bytes;
     hipStream_t stream;
-    BatchEntry *staging;   // pinned host
+    void *staging;         // pinned host: BatchEntry or WholeEntry records
     hipEvent_t staged;     // recorded after the last staging copy
     bool persistent_used;  // a persistent launch ran since the last check
 };
@@ -228,13 +231,13 @@ int32_t launch_end(const isf_lattice *lat) {
 // The spare copy gets the film's layout (its vacancies) once, before its
 // first use; after a whole sweep the state may sit in the spare copy, and
 // settle() moves it back before anything else reads or writes the spins.
-int32_t prepare_spare(isf_lattice *lat) {
+int32_t prepare_spare(isf_lattice *lat, const Tiling &tl) {
     if (!lat->spare_ready) {
         HIP_TRY(hipMemcpyAsync(lat->spare, lat->L.spins, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice,
                                lat->stream));
         lat->spare_ready = true;
     }
-    const Tiling &tl = lat->tiling, &lt = lat->lists_tiling;
+    const Tiling &lt = lat->lists_tiling;
     if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty) {
         hipError_t e = launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
         if (e != hipSuccess)
@@ -349,7 +352,7 @@ int32_t build_graph(isf_lattice *lat) {
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     int32_t rc0;
     if (lat->tiling.kernel == ISF_KERNEL_SWEEP) {
-        if ((rc0 = prepare_spare(lat)) || (rc0 = prime_whole(lat)))
+        if ((rc0 = prepare_spare(lat, lat->tiling)) || (rc0 = prime_whole(lat)))
             return rc0;
         // graphs hold an even number of whole sweeps and start from the main copy
         if (lat->cur_spare && n > 0) {
@@ -1002,7 +1005,7 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     int32_t status = ISF_OK;
     const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
-    if (whole ? ((rc = prepare_spare(lat)) || (rc = prime_whole(lat))) : (rc = settle(lat)) != 0) {
+    if (whole ? ((rc = prepare_spare(lat, lat->tiling)) || (rc = prime_whole(lat))) : (rc = settle(lat)) != 0) {
         for (auto &e : ev)
             (void)hipEventDestroy(e);
         return rc;
@@ -1063,10 +1066,32 @@ int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E) {
 // ---------------------------------------------------------------------------
 // batches
 
+}  // extern "C"
+
+namespace {
+
+// Batch workspace on the device: the launch table, the first block of every
+// film (whole-sweep mode), then the persistent kernel's barrier words.
+struct WsLayout {
+    uint64_t begins, barrier, total;
+};
+WsLayout ws_layout(uint32_t max_lats) {
+    auto up = [](uint64_t v) { return (v + 255) / 256 * 256; };
+    WsLayout w;
+    w.begins = up(std::max(sizeof(BatchEntry), sizeof(WholeEntry)) * max_lats);
+    w.barrier = w.begins + up(sizeof(uint32_t) * ((uint64_t)max_lats + 1));
+    w.total = w.barrier + 256;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t isf_batch_workspace_bytes(uint32_t max_lats, uint64_t *bytes) {
     if (!bytes || max_lats == 0)
         return fail(ISF_EINVAL, "bad arguments");
-    *bytes = ((uint64_t)sizeof(BatchEntry) * max_lats + 256 + 255) / 256 * 256;
+    *bytes = ws_layout(max_lats).total;
     return ISF_OK;
 }
 
@@ -1089,7 +1114,7 @@ int32_t isf_batch_create(uint32_t max_lats, void *ws, uint64_t ws_bytes, void *s
     b->ws_dev = static_cast<uint8_t *>(ws);
     b->ws_bytes = ws_bytes;
     b->stream = static_cast<hipStream_t>(stream);
-    if (hipHostMalloc((void **)&b->staging, sizeof(BatchEntry) * max_lats, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&b->staging, ws_layout(max_lats).barrier, hipHostMallocDefault) != hipSuccess) {
         delete b;
         return fail(ISF_EHIP, "hipHostMalloc of the staging area failed");
     }
@@ -1118,7 +1143,7 @@ int32_t isf_batch_sync(isf_batch *b) {
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (b->persistent_used) {
         uint32_t flag = 0;
-        HIP_TRY(hipMemcpy(&flag, b->ws_dev + sizeof(BatchEntry) * b->max_lats + sizeof(uint32_t), sizeof flag,
+        HIP_TRY(hipMemcpy(&flag, b->ws_dev + ws_layout(b->max_lats).barrier + sizeof(uint32_t), sizeof flag,
                           hipMemcpyDeviceToHost));
         if (flag)
             return fail(ISF_EHIP, "persistent kernel: grid barrier timed out; results are invalid");
@@ -1126,13 +1151,102 @@ int32_t isf_batch_sync(isf_batch *b) {
     return ISF_OK;
 }
 
+namespace {
+
+// Batched whole-sweep mode: one launch per sweep over the tiles of every film.
+int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps,
+                            uint64_t *enqueued_out) {
+    const Tiling tl = lats[0]->tiling.kernel == ISF_KERNEL_SWEEP ? lats[0]->tiling : Tiling{16, 16, 4, ISF_KERNEL_SWEEP};
+    uint32_t Zmax = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (lats[i]->d.format != ISF_FORMAT_INT8 || !lats[i]->spare)
+            return fail(ISF_EINVAL, "whole-sweep batches need INT8 lattices");
+        Zmax = std::max(Zmax, lats[i]->d.Z);
+    }
+    const uint32_t lds = halo_lds_bytes(tl.tx, tl.ty, Zmax);
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lats[0]->device));
+    if (lds == 0 || lds > (uint32_t)max_lds - 4096u || halo_region_dwords(tl.tx, tl.ty, Zmax) > 65536u ||
+        (tl.ry != 4 && tl.ry != 8 && tl.ry != 16))
+        return fail(ISF_EINVAL, "whole-sweep shape %ux%u x %u waves does not fit films of %u planes", tl.tx, tl.ty,
+                    tl.ry, Zmax);
+    // each film: its spare copy and lists for the shape, and an open run of whole sweeps
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        if (lat->sched_total == lat->sched_enqueued)
+            continue;
+        const bool ready = lat->spare_ready && lat->lists_ready && lat->lists_tiling.tx == tl.tx &&
+                           lat->lists_tiling.ty == tl.ty && lat->whole_active;
+        if (ready)
+            continue;
+        int32_t rc;
+        if ((rc = prepare_spare(lat, tl)) || (rc = prime_whole(lat)))
+            return rc;
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+    }
+    HIP_TRY(hipEventSynchronize(b->staged));  // the staging area may still be read by the previous copy
+    WholeEntry *stage = static_cast<WholeEntry *>(b->staging);
+    const WsLayout wl = ws_layout(b->max_lats);
+    uint32_t *stage_begins = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b->staging) + wl.begins);
+    uint64_t sweeps = 0;
+    uint32_t m = 0, blocks = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        const uint64_t rem = lat->sched_total - lat->sched_enqueued;
+        if (rem == 0)
+            continue;
+        WholeEntry &e = stage[m++];
+        e.lat = lat->L;
+        e.spare = lat->spare;
+        e.lists = lat->lists;
+        e.block_begin = blocks;
+        stage_begins[m - 1] = blocks;
+        e.po = lat->cur_spare ? 1u : 0u;
+        e.pad = 0;
+        blocks += halo_tiles(tl.tx, tl.ty, lat->L.nd, lat->L.Y, e.nbx);
+        sweeps = std::max<uint64_t>(sweeps, std::min<uint64_t>(rem, max_sweeps));
+    }
+    if (m == 0 || sweeps == 0) {
+        if (enqueued_out)
+            *enqueued_out = 0;
+        return ISF_OK;
+    }
+    stage_begins[m] = blocks;
+    WholeEntry *ents = reinterpret_cast<WholeEntry *>(b->ws_dev);
+    const uint32_t *begins = reinterpret_cast<const uint32_t *>(b->ws_dev + wl.begins);
+    HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(WholeEntry) * m, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->ws_dev + wl.begins, stage_begins, sizeof(uint32_t) * (m + 1), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipEventRecord(b->staged, b->stream));
+    for (uint64_t g = 0; g < sweeps; ++g) {
+        hipError_t e =
+            launch_sweep_i8_halo_batch(ents, begins, m, blocks, tl, Zmax, (uint32_t)(g & 1u), b->stream);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
+    }
+    // a film past its schedule's end sits out the remaining launches: its spins
+    // moved once per sweep it ran
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        const uint64_t ran = std::min<uint64_t>(lat->sched_total - lat->sched_enqueued, sweeps);
+        if (ran & 1u)
+            lat->cur_spare = !lat->cur_spare;
+        lat->sched_enqueued += ran;
+    }
+    if (enqueued_out)
+        *enqueued_out = sweeps;
+    return ISF_OK;
+}
+
+}  // namespace
+
 int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps, int32_t mode,
                           uint64_t *enqueued_out) {
     if (!b || (n && !lats))
         return fail(ISF_EINVAL, "null pointer argument");
     if (n > b->max_lats)
         return fail(ISF_EINVAL, "%u lattices exceed the batch capacity %u", n, b->max_lats);
-    if (mode != ISF_BATCH_PHASE_LAUNCH && mode != ISF_BATCH_PERSISTENT)
+    if (mode != ISF_BATCH_PHASE_LAUNCH && mode != ISF_BATCH_PERSISTENT && mode != ISF_BATCH_WHOLE)
         return fail(ISF_EINVAL, "unknown batch mode %d", mode);
     if (n == 0) {
         if (enqueued_out)
@@ -1148,6 +1262,8 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
         if (lats[i]->d.format != format)
             return fail(ISF_ESTATE, "lattices of a batch must share one format");
     }
+    if (mode == ISF_BATCH_WHOLE)
+        return batch_advance_whole(b, lats, n, max_sweeps, enqueued_out);
     // batch kernels work on the main copy of the spins
     for (uint32_t i = 0; i < n; ++i)
         if (lats[i]->cur_spare || lats[i]->whole_active) {
@@ -1165,7 +1281,7 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
         const uint64_t rem = lat->sched_total - lat->sched_enqueued;
         if (rem == 0)
             continue;
-        BatchEntry &e = b->staging[m++];
+        BatchEntry &e = static_cast<BatchEntry *>(b->staging)[m++];
         e.lat = lat->L;
         e.block_begin = blocks;
         if (format == ISF_FORMAT_INT8)
@@ -1181,7 +1297,7 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
         return ISF_OK;
     }
     BatchEntry *ents = reinterpret_cast<BatchEntry *>(b->ws_dev);
-    uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + sizeof(BatchEntry) * b->max_lats);
+    uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + ws_layout(b->max_lats).barrier);
     HIP_TRY(hipMemcpyAsync(ents, b->staging, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipEventRecord(b->staged, b->stream));
     if (mode == ISF_BATCH_PHASE_LAUNCH) {
@@ -1234,8 +1350,8 @@ int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n, const 
     for (uint32_t i = 0; i < n; ++i) {
         if (n_steps[i] && !out[i])
             return fail(ISF_EINVAL, "null record buffer %u", i);
-        if (n_steps[i])
-            HIP_TRY(hipMemcpy(out[i], lats[i]->L.records, sizeof(isf_record) * n_steps[i], hipMemcpyDeviceToHost));
+        if ((rc = isf_schedule_records(lats[i], out[i], n_steps[i])))
+            return rc;
     }
     return ISF_OK;
 }

@@ -238,7 +238,8 @@ __device__ __forceinline__ void block_add4(int64_t *out, int64_t a, int64_t b, i
 }
 
 // Linear block index -> film entry of a batched launch table (binary search).
-__device__ __forceinline__ uint32_t find_entry(const BatchEntry *ents, uint32_t n, uint32_t b) {
+template <typename Entry>
+__device__ __forceinline__ uint32_t find_entry(const Entry *ents, uint32_t n, uint32_t b) {
     uint32_t lo = 0, hi = n;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;

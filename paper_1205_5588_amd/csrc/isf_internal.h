@@ -136,4 +136,15 @@ struct BatchEntry {
     uint32_t nbx, nby, nbz;  // block grid of this film for the launch's phase
 };
 
+// One film in a batched whole-sweep launch.
+struct WholeEntry {
+    LatDev lat;
+    uint8_t *spare;        // the film's second spin copy
+    const uint8_t *lists;  // its per-tile lists for the launch's shape
+    uint32_t block_begin;  // first linear block (= tile 0) of this film
+    uint32_t nbx;          // tiles along a row
+    uint32_t po;           // sweep parity of the film at the launch with g = 0
+    uint32_t pad;
+};
+
 }  // namespace isf

@@ -224,15 +224,18 @@ __device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, cons
                 }
             }
         }
+        // a launch after the film's schedule ended (batches) is no sweep: the
+        // position stays and nothing waits to be folded
+        const uint32_t ran = bk.w[14];
         SweepPos &np = L.pos[1 - cur];
-        np.t = (uint64_t)w64(bk, 8) + 1;
+        np.t = (uint64_t)w64(bk, 8) + ran;
         np.step = step;
         np.sis = sis;
         np.n_sweeps = ns;
         np.n_discard = nd;
         np.run = run;
         np.pending = 0;
-        L.pos[cur].pending = 1;  // this sweep's slots wait for the next fold
+        L.pos[cur].pending = ran;  // this sweep's slots wait for the next fold
     }
     next_step = __shfl(next_step, 0, 64);
     if (lane < kTableWords)
@@ -338,10 +341,12 @@ __global__ __launch_bounds__(256) void k_sweep_lists(LatDev L, uint32_t nbx, uin
         reinterpret_cast<uint32_t *>(rec)[tid] = cnt[tid];
 }
 
+// One tile of one whole sweep of parity q (the body of the plain and the
+// batched kernels).  The block with tile 0 of the film keeps its books.
 template <int TXD, int TYR, int NT>
-__global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *__restrict__ src,
-                                                      uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
-                                                      uint32_t nbx, uint32_t per_xcd, uint32_t q) {
+__device__ __forceinline__ void sweep_tile(const LatDev &L, const uint8_t *__restrict__ src,
+                                           uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
+                                           uint32_t nbx, uint32_t tile, uint32_t q) {
     using G = Geo<TXD, TYR>;
     constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL;
     extern __shared__ __align__(16) uint8_t smb[];
@@ -357,16 +362,11 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
     uint32_t *dmap = reinterpret_cast<uint32_t *>(smb + G::off_dmap(Z));  // global dword, bit 31: tile dword
     uint16_t *lst = reinterpret_cast<uint16_t *>(smb + G::off_lst(Z));
 
-    const uint32_t b = blockIdx.x;
-    const uint32_t tile = tile_of_block(b, per_xcd);
-    const uint32_t nby = (Y + TYR - 1) / TYR;
-    if (tile >= nbx * nby)
-        return;  // uniform: grid padding to a multiple of 8
     const uint32_t bx = tile % nbx, by = tile / nbx;
     const uint32_t d0 = bx * TXD, y0 = by * TYR;
     const uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
     const uint4 cnt = *reinterpret_cast<const uint4 *>(rec);  // uniform: a scalar load
-    const bool booker = b == 0 && tid < 64;                   // wave 0 of block 0 keeps the books
+    const bool booker = tile == 0 && tid < 64;                // wave 0 of tile 0's block keeps the books
     __shared__ BookLds bk;
     BookRegs br;
     if (booker)
@@ -598,11 +598,42 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *_
                 *reinterpret_cast<uint32_t *>(out + p * planeb + (ym & 0x7FFFFFFFu) * rowb + (dm & 0x7FFFFFFFu) * 4u) = v;
         }
     }
-    finish_block_to<NT>(slots_of(L, q), dM, dE, acc, b);
+    finish_block_to<NT>(slots_of(L, q), dM, dE, acc, tile);
     if (booker) {
         book_fold(L, 1 - q, bk, tid);
         book_advance(L, q, bk, tab, tid);
     }
+}
+
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_halo(LatDev L, const uint8_t *__restrict__ src,
+                                                      uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
+                                                      uint32_t nbx, uint32_t per_xcd, uint32_t q) {
+    const uint32_t tile = tile_of_block(blockIdx.x, per_xcd);
+    if (tile >= nbx * ((L.Y + TYR - 1) / TYR))
+        return;  // uniform: grid padding to a multiple of 8
+    sweep_tile<TXD, TYR, NT>(L, src, dst, lists, nbx, tile, q);
+}
+
+// Batched: one launch covers one sweep of every film of a batch; block b
+// works on the film whose block range [begins[f], begins[f + 1]) holds it,
+// found by all threads of the block in one pass over the range starts.  Film
+// f's sweep parity is (g ^ po_f) & 1 for the launch's sweep index g.
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_halo_batch(const WholeEntry *__restrict__ ents,
+                                                            const uint32_t *__restrict__ begins, uint32_t n_ents,
+                                                            uint32_t g) {
+    __shared__ uint32_t ent_sh;
+    const uint32_t b = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < n_ents; i += NT)
+        if (begins[i] <= b && b < begins[i + 1])
+            ent_sh = i;  // exactly one film's range holds b
+    __syncthreads();
+    const WholeEntry &e = ents[ent_sh];
+    const uint32_t q = (g ^ e.po) & 1u;
+    uint8_t *main_copy = e.lat.spins, *spare = e.spare;
+    sweep_tile<TXD, TYR, NT>(e.lat, q ? spare : main_copy, q ? main_copy : spare, e.lists, e.nbx, b - e.block_begin,
+                             q);
 }
 
 namespace {
@@ -630,6 +661,22 @@ hipError_t launch_halo_t(const LatDev &L, const uint8_t *src, uint8_t *dst, cons
     else
         hipLaunchKernelGGL((k_sweep_i8_halo<TXD, TYR, 256>), grid, dim3(256), lds, s, L, src, dst, lists, nbx,
                            per_xcd, q);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+hipError_t launch_halo_batch_t(const WholeEntry *ents, const uint32_t *begins, uint32_t n_ents, uint32_t blocks,
+                               uint32_t Zmax, uint32_t nt, uint32_t g, hipStream_t s) {
+    const size_t lds = Geo<TXD, TYR>::lds_bytes(Zmax);
+    if (nt == 1024)
+        hipLaunchKernelGGL((k_sweep_i8_halo_batch<TXD, TYR, 1024>), dim3(blocks), dim3(1024), lds, s, ents, begins,
+                           n_ents, g);
+    else if (nt == 512)
+        hipLaunchKernelGGL((k_sweep_i8_halo_batch<TXD, TYR, 512>), dim3(blocks), dim3(512), lds, s, ents, begins,
+                           n_ents, g);
+    else
+        hipLaunchKernelGGL((k_sweep_i8_halo_batch<TXD, TYR, 256>), dim3(blocks), dim3(256), lds, s, ents, begins,
+                           n_ents, g);
     return hipGetLastError();
 }
 
@@ -721,6 +768,26 @@ hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s) {
 hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s) {
     hipLaunchKernelGGL(k_whole_flush, dim3(1), dim3(64), 0, s, L, q_last);
     return hipGetLastError();
+}
+
+// Tiles of a film for a whole-sweep shape (0 if not a compiled shape).
+uint32_t halo_tiles(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t &nbx) {
+    if (halo_lds_bytes(tx, ty, 1) == 0)
+        return 0;
+    nbx = (nd + tx - 1) / tx;
+    return nbx * ((Y + ty - 1) / ty);
+}
+
+// One sweep of every film of a batch (sweep index g; Zmax: the largest film depth).
+hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *begins, uint32_t n_ents,
+                                      uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s) {
+    const uint32_t nt = 64u * tl.ry;
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_halo_batch_t<A, B>(ents, begins, n_ents, blocks, Zmax, nt, g, s);
+    ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace isf

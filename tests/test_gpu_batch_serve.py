@@ -29,7 +29,7 @@ def isf():
     return lattice
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_config_batched_sampled(isf, mode):
     """All 256 replicas of the batched workload on a prefix of the ramp: batched ==
     alone for a spread of replicas, and the smallest films == oracle over the
@@ -105,7 +105,7 @@ def _small_requests(n=10):
     return reqs
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_serving_alone_equals_in_mix(isf, mode):
     from paper_1205_5588_amd.serve import GpuExecutor, Job, Server, request_schedule
 

@@ -272,9 +272,11 @@ def _batch_films(isf, fmt=0):
     return films
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_batched_equals_alone_and_oracle(isf, mode, fmt):
+    if mode == 2 and fmt == 1:
+        pytest.skip("whole-sweep batches take INT8 films (rejection tested separately)")
     films = _batch_films(isf)
     if fmt == 1:
         films = [(np.tile(h, (1, 2))[:, : max(64, (h.shape[1] // 64) * 64)], Z, s, r, sc)
@@ -289,15 +291,22 @@ def test_batched_equals_alone_and_oracle(isf, mode, fmt):
         np.testing.assert_array_equal(lat.spins(), o.spins())
 
 
-def test_batched_incremental_chunks(isf):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batched_incremental_chunks(isf, mode):
     films = _batch_films(isf)
     lats = [isf.Lattice(h, Z, s, replica=r, init=2) for (h, Z, s, r, sc) in films]
-    _say("batch chunks")
+    _say("batch chunks", mode)
     for lat, f in zip(lats, films):
         lat.schedule_load(f[4])
     b = isf.Batch(len(lats))
+    k = 0
     while any(l.remaining() for l in lats):
-        b.advance(lats, 3, mode=0)
+        # odd chunk lengths, and a film read between chunks, close and reopen whole-sweep runs
+        b.advance(lats, 3 if k % 2 == 0 else 2, mode=mode)
+        b.sync()
+        if k == 1:
+            lats[1].observables()
+        k += 1
     b.sync()
     for (h, Z, s, r, sc), lat in zip(films, lats):
         o = cpu.Film(h, Z, s, r, init=2)
@@ -446,3 +455,13 @@ def test_sweep_kernel_switches_and_reads_midway(isf):
     ro = np.array([o.run(*s).as_tuple() for s in steps])
     np.testing.assert_array_equal(g.records(), ro)
     _assert_same(g, o)
+
+
+def test_batched_whole_mode_rejects_bitpack(isf):
+    from paper_1205_5588_amd._lib import IsfError
+
+    h = _rand_h((16, 128), 3, 5)
+    lats = [isf.Lattice(h, 3, 1, fmt=1)]
+    lats[0].schedule_load([(2.0, 0, 2, 0)])
+    with pytest.raises(IsfError):
+        isf.Batch(1).advance(lats, 2, mode=2)
