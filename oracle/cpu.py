@@ -46,6 +46,11 @@ def lib():
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
                               ctypes.c_uint32, ctypes.POINTER(Record)]
         L.orc_run.restype = ctypes.c_int
+        L.orc_run_gated.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.orc_run_gated.restype = ctypes.c_int
+        L.orc_gate_threshold.argtypes = [ctypes.c_int32, ctypes.c_double]
+        L.orc_gate_threshold.restype = ctypes.c_uint32
         L.orc_get_spins.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_set_spins.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
         L.orc_set_spins.restype = ctypes.c_int
@@ -74,6 +79,10 @@ def threshold_table(T: float, h_num: int) -> np.ndarray:
     out = np.zeros((2, 25), dtype=np.uint32)
     lib().orc_threshold_table(float(T), int(h_num), out.ctypes.data)
     return out
+
+
+def gate_threshold(T: float, hs_num: int) -> int:
+    return int(lib().orc_gate_threshold(int(hs_num), float(T)))
 
 
 def set_threads(n: int) -> None:
@@ -107,9 +116,11 @@ class Film:
     def set_order(self, order: int) -> None:
         lib().orc_set_order(self._p, int(order))
 
-    def run(self, T: float, h_num: int, n_sweeps: int, n_discard: int = 0) -> Record:
+    def run(self, T: float, h_num: int, n_sweeps: int, n_discard: int = 0, hs_num: int = 0) -> Record:
+        """n_sweeps sweeps at (T, H = h_num/20), behind the switching-field gate of h_s = hs_num/20."""
         r = Record()
-        rc = lib().orc_run(self._p, float(T), int(h_num), int(n_sweeps), int(n_discard), ctypes.byref(r))
+        rc = lib().orc_run_gated(self._p, float(T), int(h_num), int(hs_num), int(n_sweeps), int(n_discard),
+                                 ctypes.byref(r))
         if rc != 0:
             raise ValueError("oracle: invalid run arguments")
         return r

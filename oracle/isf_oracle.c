@@ -30,7 +30,14 @@
  *   - the draw for site (x, y, z) in sweep t is word (k mod 4) of
  *     Philox4x32-10 with key (seed mod 2^32, seed div 2^32) and counter
  *     (k div 4, t, replica, sigma + 4 tag), k = (z Y + y)(X/2) + x div 2,
- *     tag 0 for Metropolis and 1 for the random start;
+ *     tag 0 for Metropolis, 1 for the random start and 2 for the
+ *     switching-field gate;
+ *   - switching-field gate (Eq. 9, steps 4-5 of the algorithm in Section 5):
+ *     with h_s = hs_num / 20 (the field's units), a site may attempt the
+ *     Metropolis move only if its gate draw u_g < floor(2^32 exp(-|h_s|/T));
+ *     hs_num = 0 switches the gate off (probability 1).  The gate draw and the
+ *     Metropolis draw both exist for every site, so the order of the two tests
+ *     does not matter: the flip happens iff both pass, for downhill moves too;
  *   - one sweep visits the four sublattices sigma = (y mod 2) + 2 (z mod 2)
  *     in the order 0, 1, 2, 3; every occupied site of the sublattice gets one
  *     attempt.
@@ -88,6 +95,17 @@ uint32_t orc_threshold(int32_t q, double T)
         return 0xFFFFFFFFu;
     double dE = (double)q / 10.0;
     double p = exp(-dE / T);
+    return (uint32_t)floor(ldexp(p, 32));
+}
+
+/* Threshold of the switching-field gate, Eq. (9): floor(2^32 exp(-|h_s|/T)),
+ * h_s = hs_num / 20; hs_num = 0 gives the sentinel (the gate always passes). */
+uint32_t orc_gate_threshold(int32_t hs_num, double T)
+{
+    if (hs_num == 0)
+        return 0xFFFFFFFFu;
+    double hs = fabs((double)hs_num) / 20.0;
+    double p = exp(-hs / T);
     return (uint32_t)floor(ldexp(p, 32));
 }
 
@@ -249,11 +267,14 @@ void orc_init(orc_film *f, int mode)
 
 void orc_set_order(orc_film *f, int order) { f->order = order; }
 
-/* One Metropolis attempt at an occupied site (steps 1-3 of Section 5). */
-static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const uint32_t thr[2][25],
+/* One Metropolis attempt at an occupied site (steps 1-3 of Section 5),
+ * behind the switching-field gate (steps 4-5) when gate != sentinel. */
+static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const uint32_t thr[2][25], uint32_t gate,
                     int64_t *dM, int64_t *dE, int64_t *acc)
 {
     size_t c = cell(f, x, y, z);
+    if (gate != 0xFFFFFFFFu && !(draw(f, x, y, z, (uint32_t)f->t, 2u) < gate))
+        return;                              /* the gate keeps the spin's orientation */
     int s = f->s[c];
     int n = neighbour_sum(f, x, y, z);
     int32_t q = s * (20 * n + h_num);      /* 10 * (E2 - E1) */
@@ -273,7 +294,7 @@ static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const uint3
 }
 
 /* One sweep at (T, h_num): sublattices 0..3 in turn.  Returns accepted flips. */
-static int64_t sweep(orc_film *f, int32_t h_num, const uint32_t thr[2][25])
+static int64_t sweep(orc_film *f, int32_t h_num, const uint32_t thr[2][25], uint32_t gate)
 {
     int64_t acc_total = 0;
     for (int sigma = 0; sigma < 4; ++sigma) {
@@ -295,7 +316,7 @@ static int64_t sweep(orc_film *f, int32_t h_num, const uint32_t thr[2][25])
             for (int xi = 0; xi < f->X; ++xi) {
                 int x = f->order == 1 ? f->X - 1 - xi : xi;
                 if (f->occ[cell(f, x, y, z)])
-                    attempt(f, x, y, z, h_num, thr, &dM, &dE, &acc);
+                    attempt(f, x, y, z, h_num, thr, gate, &dM, &dE, &acc);
             }
         }
         f->M += dM;
@@ -317,7 +338,9 @@ typedef struct {
     int64_t accepted;
 } orc_record;
 
-int orc_run(orc_film *f, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_discard, orc_record *rec)
+/* n_sweeps sweeps at (T, h_num) behind the switching-field gate of hs_num. */
+int orc_run_gated(orc_film *f, double T, int32_t h_num, int32_t hs_num, uint32_t n_sweeps, uint32_t n_discard,
+                  orc_record *rec)
 {
     if (!(T > 0.0) || n_discard > n_sweeps)
         return -1;
@@ -325,10 +348,11 @@ int orc_run(orc_film *f, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_
         return -1;
     uint32_t thr[2][25];
     orc_threshold_table(T, h_num, thr);
+    const uint32_t gate = orc_gate_threshold(hs_num, T);
     orc_record r;
     memset(&r, 0, sizeof r);
     for (uint32_t i = 0; i < n_sweeps; ++i) {
-        int64_t acc = sweep(f, h_num, thr);
+        int64_t acc = sweep(f, h_num, thr, gate);
         if (i >= n_discard) {
             r.sum_M += f->M;
             r.sum_absM += f->M < 0 ? -f->M : f->M;
@@ -341,6 +365,12 @@ int orc_run(orc_film *f, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_
     if (rec)
         *rec = r;
     return 0;
+}
+
+/* n_sweeps sweeps at (T, h_num) without the gate (steps 1-3 only). */
+int orc_run(orc_film *f, double T, int32_t h_num, uint32_t n_sweeps, uint32_t n_discard, orc_record *rec)
+{
+    return orc_run_gated(f, T, h_num, 0, n_sweeps, n_discard, rec);
 }
 
 void orc_get_spins(const orc_film *f, int8_t *cube)

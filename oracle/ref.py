@@ -7,6 +7,7 @@ check each other on small films.
 Contents:
   philox4x32_10      -- Philox4x32-10 (Salmon et al., SC 2011) on Python ints
   threshold          -- Eq. (8) threshold floor(2^32 exp(-(q/10)/T)) via math.exp
+  gate_threshold     -- Eq. (9) switching-field gate floor(2^32 exp(-|h_s|/T)), h_s = hs_num/20
   TinyFilm           -- the sweep of Section 5 (steps 1-3) on a site list
   enumerate_exact    -- partition function of Eq. (4) and Gibbs averages of
                         Eq. (5) by enumerating all 2^N configurations
@@ -45,6 +46,21 @@ def threshold(q: int, T: float) -> int:
     if q <= 0:
         return M32
     return int(math.floor(math.ldexp(math.exp(-(q / 10.0) / T), 32)))
+
+
+def gate_threshold(hs_num: int, T: float) -> int:
+    """32-bit threshold of the switching-field gate (hs_num = 0: sentinel, the gate always passes)."""
+    if hs_num == 0:
+        return M32
+    return int(math.floor(math.ldexp(math.exp(-(abs(hs_num) / 20.0) / T), 32)))
+
+
+def gate_probability(hs_num: int, T: float, quantised: bool = True) -> float:
+    if hs_num == 0:
+        return 1.0
+    if quantised:
+        return gate_threshold(hs_num, T) / 2.0**32
+    return math.exp(-(abs(hs_num) / 20.0) / T)
 
 
 def accept_probability(q: int, T: float, quantised: bool = True) -> float:
@@ -109,11 +125,16 @@ class TinyFilm:
     def bond_energy(self) -> int:
         return -sum(self.s[i] * self.s[j] for i, j in self.bonds)
 
-    def sweep(self, T: float, h_num: int) -> int:
+    def sweep(self, T: float, h_num: int, hs_num: int = 0) -> int:
+        """One sweep; with hs_num != 0 each attempt first passes the switching-field
+        gate of Eq. (9) (steps 4-5 of Section 5) with its own draw (tag 2)."""
         acc = 0
+        g = gate_threshold(hs_num, T)
         for sigma in range(4):
             for i in range(self.N):
                 if self.sub[i] != sigma:
+                    continue
+                if g != M32 and not self.draw(i, self.t, 2) < g:
                     continue
                 n = sum(self.s[j] for j in self.nbrs[i])
                 q = self.s[i] * (20 * n + h_num)
@@ -165,8 +186,11 @@ def boltzmann(film: TinyFilm, T: float, h_num: int) -> Tuple[List[Tuple[int, ...
     return states, w / w.sum()
 
 
-def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bool = True) -> np.ndarray:
-    """Transition matrix of one sublattice phase: its sites are updated independently."""
+def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bool = True,
+                 hs_num: int = 0) -> np.ndarray:
+    """Transition matrix of one sublattice phase: its sites are updated independently;
+    a site flips if its switching-field gate (probability g) and the Metropolis test pass."""
+    g = gate_probability(hs_num, T, quantised)
     states = list(itertools.product((-1, 1), repeat=film.N))
     idx = {st: a for a, st in enumerate(states)}
     P = np.zeros((len(states), len(states)))
@@ -176,7 +200,7 @@ def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bo
         probs = []
         for i in members:
             n = sum(st[j] for j in film.nbrs[i])
-            probs.append(accept_probability(st[i] * (20 * n + h_num), T, quantised))
+            probs.append(g * accept_probability(st[i] * (20 * n + h_num), T, quantised))
         for flips in itertools.product((0, 1), repeat=len(members)):
             pr = 1.0
             new = list(st)
@@ -188,8 +212,8 @@ def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bo
     return P
 
 
-def sweep_matrix(film: TinyFilm, T: float, h_num: int, quantised: bool = True) -> np.ndarray:
+def sweep_matrix(film: TinyFilm, T: float, h_num: int, quantised: bool = True, hs_num: int = 0) -> np.ndarray:
     P = np.eye(2**film.N)
     for sigma in range(4):
-        P = P @ phase_matrix(film, T, h_num, sigma, quantised)
+        P = P @ phase_matrix(film, T, h_num, sigma, quantised, hs_num)
     return P

@@ -383,3 +383,138 @@ def test_table1_critical_concentration():
         assert round(physics.critical_concentration(z), 2) == pytest.approx(pc, abs=1e-9)
         # single bond counting: mean-field Tc = z J lies above the printed Tc in every row
         assert tc < z
+
+
+# --------------------------------------------------------------------------- switching-field gate (Eq. 9)
+# The gate's probability exp(-|S_i h_s|/T) does not depend on the spin, so it
+# multiplies every flip probability by the same factor g: detailed balance and
+# the Boltzmann stationary law of Eq. (3) are unchanged, only the dynamics slow
+# down.  These pins check that, the gate thresholds, and the gate's own draw.
+def test_gate_thresholds_against_high_precision_exp(oracle_lib):
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    for T in (1e-3, 0.5, 1.0, 3.0, 7.3, 12.0, 1e6):
+        assert cpu.gate_threshold(T, 0) == 0xFFFFFFFF == ref.gate_threshold(0, T)
+        for hs in (1, 7, 40, 80, 160, 4000):
+            thr = cpu.gate_threshold(T, hs)
+            assert thr == cpu.gate_threshold(T, -hs) == ref.gate_threshold(hs, T)
+            exact = mpmath.exp(-mpmath.mpf(hs) / 20 / T) * 2**32
+            assert abs(thr - int(mpmath.floor(exact))) <= 1, (T, hs)
+            assert thr <= 2**32 - 215  # never the sentinel
+    assert cpu.gate_threshold(1e-3, 1) == 0
+
+
+def test_gated_transition_matrices():
+    for (h, Z) in _pair_and_triangle():
+        film = ref.TinyFilm(h, Z)
+        for T, hn, hs in ((1.5, 10, 30), (3.0, -40, 160), (0.7, 5, 7)):
+            states, pi = ref.boltzmann(film, T, hn)
+            g = ref.gate_probability(hs, T, quantised=False)
+            for sigma in range(4):
+                for quant, tol in ((False, 1e-15), (True, 2.0**-31)):
+                    P = ref.phase_matrix(film, T, hn, sigma, quantised=quant, hs_num=hs)
+                    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-15)
+                    flow = pi[:, None] * P
+                    assert np.max(np.abs(flow - flow.T)) <= tol
+                # off-diagonal single flips are the ungated ones times g
+                P0 = ref.phase_matrix(film, T, hn, sigma, quantised=False)
+                P1 = ref.phase_matrix(film, T, hn, sigma, quantised=False, hs_num=hs)
+                n_members = sum(1 for s in film.sub if s == sigma)
+                if n_members == 1:
+                    off = ~np.eye(len(states), dtype=bool)
+                    assert np.allclose(P1[off], g * P0[off], atol=1e-15)
+            S = ref.sweep_matrix(film, T, hn, quantised=False, hs_num=hs)
+            assert np.max(np.abs(pi @ S - pi)) <= 1e-14
+
+
+def test_gated_transition_frequencies_sampled(oracle_lib):
+    """One-sweep frequencies of the gated C oracle against the gated quantised sweep matrix."""
+    h, Z = _pair_and_triangle()[1]
+    film = ref.TinyFilm(h, Z)
+    T, hn, hs = 1.5, 10, 30
+    S = ref.sweep_matrix(film, T, hn, quantised=True, hs_num=hs)
+    S0 = ref.sweep_matrix(film, T, hn, quantised=True)
+    states = [tuple(s) for s in __import__("itertools").product((-1, 1), repeat=film.N)]
+    idx = {s: a for a, s in enumerate(states)}
+    start = (1, -1, 1)
+    assert np.max(np.abs(S[idx[start]] - S0[idx[start]])) > 0.05  # the gate changes this row
+    f = cpu.Film(h, Z, seed=4242, replica=3)
+    cube = np.zeros((Z, 4, 4), dtype=np.int8)
+    for i, (x, y, z) in enumerate(film.sites):
+        cube[z, y, x] = start[i]
+    nsamp = 60000
+    counts = np.zeros(len(states))
+    for t in range(nsamp):
+        f.set_spins(cube, t)
+        f.run(T, hn, 1, 0, hs)
+        sp = f.spins()
+        counts[idx[tuple(int(sp[z, y, x]) for (x, y, z) in film.sites)]] += 1
+    p = S[idx[start]]
+    sd = np.sqrt(nsamp * p * (1 - p)) + 1e-9
+    assert np.all(np.abs(counts - nsamp * p) <= 5 * sd + 1), (counts, nsamp * p)
+    assert counts[p == 0].sum() == 0
+
+
+def test_gated_isolated_spin(oracle_lib):
+    """Two-state chain: up->down with g p, down->up with g (dE < 0 moves are gated
+    too); m = tanh(H/T) as without the gate, flip rate g 2p/(1+p) per sweep."""
+    h = np.zeros((4, 4), dtype=np.uint8)
+    h[0, 0] = 1
+    T, hn, hs = 1.0, 10, 12
+    p = cpu.lib().orc_threshold(hn, T) / 2.0**32
+    g = cpu.gate_threshold(T, hs) / 2.0**32
+    f = cpu.Film(h, 1, seed=23, init=cpu.INIT_UP)
+    nblk, blk = 40, 20000
+    ms, rates = [], []
+    for _ in range(nblk):
+        r = f.run(T, hn, blk, 0, hs)
+        ms.append(r.sum_M / blk)
+        rates.append(r.accepted / blk)
+    m_chain = (1 - p) / (1 + p)
+    assert abs(np.mean(ms) - m_chain) <= 5 * np.std(ms, ddof=1) / math.sqrt(nblk) + 1e-4
+    rate = g * 2 * p / (1 + p)
+    assert abs(np.mean(rates) - rate) <= 5 * np.std(rates, ddof=1) / math.sqrt(nblk) + 1e-4
+
+
+def test_gate_blocks_downhill_moves_at_low_temperature(oracle_lib):
+    """T -> 0 with h_s > 0: the gate's probability is 0, so not even the moves
+    that lower the energy happen (steps 4-5 come before steps 1-3)."""
+    rng = np.random.default_rng(5)
+    h = rng.integers(0, 4, size=(16, 16)).astype(np.uint8)
+    f = cpu.Film(h, 3, seed=9, init=cpu.INIT_RANDOM)
+    start = f.spins()
+    r = f.run(1e-3, 241, 5, 0, 20)
+    assert r.accepted == 0 and np.array_equal(f.spins(), start)
+    r = f.run(1e-3, 241, 1, 0, 0)  # without the gate every down spin flips
+    assert r.M == f.state()[2]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gated_c_oracle_matches_python_oracle(oracle_lib, seed):
+    rng = np.random.default_rng(300 + seed)
+    Y, X, Z = [(8, 8, 3), (6, 10, 4)][seed]
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    key = int(rng.integers(0, 2**63))
+    tf = ref.TinyFilm(h, Z, seed=key, replica=seed)
+    tf.init_random()
+    cf = cpu.Film(h, Z, key, seed, init=cpu.INIT_RANDOM)
+    for T, hn, hs in ((2.5, 20, 40), (1.1, -7, 160), (6.0, 0, -80), (0.9, 55, 3)):
+        acc = sum(tf.sweep(T, hn, hs) for _ in range(4))
+        r = cf.run(T, hn, 4, 0, hs)
+        sp = cf.spins()
+        assert all(sp[z, y, x] == tf.s[i] for i, (x, y, z) in enumerate(tf.sites))
+        assert r.M == tf.magnetisation() and r.E == tf.bond_energy() and r.accepted == acc
+
+
+def test_gated_exact_enumeration(oracle_lib):
+    """The gate leaves the Gibbs averages of Eqs. (4)-(5) unchanged (8-site film)."""
+    h, Z = _tiny_films()[0]
+    tf = ref.TinyFilm(h, Z)
+    T, hn, hs = 3.0, 45, 40
+    ex = ref.enumerate_exact(tf, T, hn)
+    f = cpu.Film(h, Z, seed=0xBEEF, replica=1)
+    f.run(T, hn, 2000, 0, hs)
+    nblk, blk = 40, 10000
+    m = [f.run(T, hn, blk, 0, hs).sum_M / blk for _ in range(nblk)]
+    se = float(np.std(m, ddof=1) / math.sqrt(nblk))
+    assert abs(float(np.mean(m)) - ex["M"]) <= 5.0 * se + 1e-3
