@@ -95,7 +95,10 @@ typedef struct {
     int32_t h_num;      /* field H = h_num / 20, |h_num| <= 200000 */
     uint32_t n_sweeps;  /* >= 1 */
     uint32_t n_discard; /* <= n_sweeps; sweeps not summed into the record */
-    uint32_t reserved;  /* must be 0 */
+    int32_t hs_num;     /* switching-field gate, Eq. 9 and steps 4-5 of Section 5: h_s = hs_num / 20,
+                           |hs_num| <= 200000; a site may flip only if its gate draw (Philox tag 2) is below
+                           floor(2^32 exp(-|h_s|/T)) and the Metropolis test passes; 0: no gate.  INT8
+                           films only (EINVAL for a bit-packed film) */
 } isf_step;
 
 typedef struct {
@@ -178,6 +181,11 @@ int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube_host, uint64_t swee
 /* Acceptance thresholds for (T, h_num): out[0][n+12] for S = -1 and
  * out[1][n+12] for S = +1, n in [-12, 12]; 0xFFFFFFFF means always accepted. */
 int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]);
+
+/* The switching-field gate's threshold floor(2^32 exp(-|hs_num/20|/T)) of
+ * Eq. 9 (0xFFFFFFFF for hs_num = 0: no gate), as the kernels use it.  EINVAL
+ * for T or |hs_num| out of range or a null output. */
+int32_t isf_gate_threshold(double T, int32_t hs_num, uint32_t *out);
 
 /* Occupied-dword lists (INT8 only).  Occupancy never changes, so for each
  * sublattice the dwords (4 compact sites) holding an occupied site can be

@@ -38,7 +38,7 @@ class Record(ctypes.Structure):
 
 class Step(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("h_num", ctypes.c_int32), ("n_sweeps", ctypes.c_uint32),
-                ("n_discard", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_discard", ctypes.c_uint32), ("hs_num", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -76,6 +76,7 @@ EXPORTS = {
     "isf_read_spins": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "isf_write_spins": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
     "isf_threshold_table": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]),
+    "isf_gate_threshold": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]),
     "isf_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "isf_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "isf_schedule_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Step), ctypes.c_uint32]),

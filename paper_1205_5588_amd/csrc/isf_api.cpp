@@ -142,13 +142,23 @@ uint32_t threshold_of(int32_t q, double T) {
     return (uint32_t)std::floor(std::ldexp(p, 32));
 }
 
-void table_of(double T, int32_t h, uint32_t *out /* kTableWords */) {
+// Threshold of the switching-field gate, Eq. (9): floor(2^32 exp(-|h_s|/T)),
+// h_s = hs / 20; hs = 0 (no gate) gives the sentinel.
+uint32_t gate_threshold_of(int32_t hs, double T) {
+    if (hs == 0)
+        return kSentinel;
+    const double p = std::exp(-(std::fabs((double)hs) / 20.0) / T);
+    return (uint32_t)std::floor(std::ldexp(p, 32));
+}
+
+void table_of(double T, int32_t h, int32_t hs, uint32_t *out /* kTableWords */) {
     for (int si = 0; si < 2; ++si) {
         const int s = si ? 1 : -1;
         for (int n = -12; n <= 12; ++n)
             out[si * 25 + n + 12] = threshold_of(s * (20 * n + h), T);
     }
-    out[50] = out[51] = 0;
+    out[kGateWord] = gate_threshold_of(hs, T);
+    out[51] = 0;
 }
 
 }  // namespace
@@ -453,8 +463,8 @@ int32_t validate_steps(const isf_step *steps, uint32_t n) {
             return fail(ISF_EINVAL, "step %u: n_sweeps must be >= 1", i);
         if (steps[i].n_discard > steps[i].n_sweeps)
             return fail(ISF_EINVAL, "step %u: n_discard > n_sweeps", i);
-        if (steps[i].reserved)
-            return fail(ISF_EINVAL, "step %u: reserved must be 0", i);
+        if (steps[i].hs_num > 200000 || steps[i].hs_num < -200000)
+            return fail(ISF_EINVAL, "step %u: |hs_num| = %d exceeds 200000", i, steps[i].hs_num);
     }
     return ISF_OK;
 }
@@ -479,6 +489,18 @@ int32_t isf_lattice_bytes(const isf_desc *d, uint64_t *spin_bytes, uint64_t *aux
     return ISF_OK;
 }
 
+int32_t isf_gate_threshold(double T, int32_t hs_num, uint32_t *out) {
+    int32_t rc = validate_T(T);
+    if (rc)
+        return rc;
+    if ((rc = validate_h(hs_num)))
+        return rc;
+    if (!out)
+        return fail(ISF_EINVAL, "null output");
+    *out = gate_threshold_of(hs_num, T);
+    return ISF_OK;
+}
+
 int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]) {
     int32_t rc = validate_T(T);
     if (rc)
@@ -488,7 +510,7 @@ int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]) {
     if (!out)
         return fail(ISF_EINVAL, "null output");
     uint32_t tab[kTableWords];
-    table_of(T, h_num, tab);
+    table_of(T, h_num, 0, tab);
     std::memcpy(out, tab, 50 * sizeof(uint32_t));
     return ISF_OK;
 }
@@ -738,7 +760,9 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) {
         sd[i] = StepDesc{steps[i].n_sweeps, steps[i].n_discard};
-        table_of(steps[i].T, steps[i].h_num, &tabs[(size_t)i * kTableWords]);
+        if (steps[i].hs_num != 0 && lat->d.format != ISF_FORMAT_INT8)
+            return fail(ISF_EINVAL, "step %u: the switching-field gate needs an INT8 film", i);
+        table_of(steps[i].T, steps[i].h_num, steps[i].hs_num, &tabs[(size_t)i * kTableWords]);
         total += steps[i].n_sweeps;
     }
     struct {

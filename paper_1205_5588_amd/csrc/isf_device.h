@@ -43,6 +43,25 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
     out[3] = c3;
 }
 
+// Switching-field gate of Eq. (9) (steps 4-5 of the algorithm in Section 5):
+// the four sites of dword k4 may flip only where their gate draws (Philox tag
+// 2: counter word 3 = sigma + 8) are below the gate threshold gthr, which is
+// word kGateWord of the table (kSentinel: no gate).  Returns the flip mask
+// (byte j = 2 where site j passes).  Uphill thresholds, gate ones included,
+// stay below kSentinel, so u < gthr is the exact test.
+__device__ __forceinline__ uint32_t gate_mask(uint32_t gthr, uint32_t k4, uint32_t t, uint32_t replica,
+                                              uint32_t sigma, uint32_t key0, uint32_t key1) {
+    if (gthr == kSentinel)
+        return 0x02020202u;
+    uint32_t g[4];
+    philox(k4, t, replica, sigma + 8u, key0, key1, g);
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        m |= g[j] < gthr ? (2u << (8 * j)) : 0u;
+    return m;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

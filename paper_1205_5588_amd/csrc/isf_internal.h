@@ -26,7 +26,8 @@
 namespace isf {
 
 constexpr uint32_t kSlots = 64;          // spread of the per-sweep atomic accumulators
-constexpr uint32_t kTableWords = 52;     // 50 thresholds, padded
+constexpr uint32_t kTableWords = 52;     // 50 thresholds, the gate threshold, padding
+constexpr uint32_t kGateWord = 50;       // switching-field gate threshold (kSentinel: no gate)
 constexpr uint32_t kDefaultMaxSteps = 1024;
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 

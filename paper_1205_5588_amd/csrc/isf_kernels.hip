@@ -146,6 +146,8 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
             F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
         }
         F &= occ << 1;
+        if (F)
+            F &= gate_mask(tab[kGateWord], pos[k], t, L.replica, sigma, L.key0, L.key1);
         if (F) {
             const uint32_t fu = F & a, fd = F ^ fu;
             const int cu = __popc(fu), cd = __popc(fd);

@@ -551,6 +551,9 @@ __device__ __forceinline__ void sweep_tile(const LatDev &L, const uint8_t *__res
                     f |= (min(u[j], 0xFFFFFFFEu) < thr) ? (2u << (8 * j)) : 0u;
                 }
                 F[k] = f & ((~a[k] & 0x01010101u) << 1);  // vacancies never flip
+                if (F[k])
+                    F[k] &= gate_mask(tab[kGateWord], kb[k] + (dm[k] & 0x7FFFFFFFu), t, L.replica, (uint32_t)s,
+                                      L.key0, L.key1);
             }
             if (!two)
                 F[1] = 0;

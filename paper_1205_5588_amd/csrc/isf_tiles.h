@@ -222,6 +222,8 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
             F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
         }
         F &= occ << 1;  // vacancies never flip
+        if (F)
+            F &= gate_mask(tab[kGateWord], k4, t, L.replica, sigma, L.key0, L.key1);
         if (F) {
             // up spins flipped: byte 2 in a & F; down spins flipped: the rest of F
             const uint32_t fu = F & a, fd = F ^ fu;

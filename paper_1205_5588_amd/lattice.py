@@ -47,10 +47,13 @@ def lattice_bytes(X: int, Y: int, Z: int, fmt: int = FORMAT_INT8) -> Tuple[int, 
     return int(s.value), int(a.value)
 
 
-def make_steps(steps: Sequence[Tuple[float, int, int, int]]):
+def make_steps(steps: Sequence[Tuple]):
+    """steps: (T, h_num, n_sweeps, n_discard[, hs_num]) each; hs_num = 0 (no switching-field gate) if absent."""
     arr = (Step * max(1, len(steps)))()
-    for i, (T, h, n, nd) in enumerate(steps):
-        arr[i] = Step(float(T), int(h), int(n), int(nd), 0)
+    for i, st in enumerate(steps):
+        T, h, n, nd = st[:4]
+        hs = st[4] if len(st) > 4 else 0
+        arr[i] = Step(float(T), int(h), int(n), int(nd), int(hs))
     return arr
 
 
@@ -135,7 +138,7 @@ class Lattice:
 
     # ------------------------------------------------------------------ runs
     def run_schedule(self, steps: Sequence[Tuple[float, int, int, int]]) -> np.ndarray:
-        """steps: (T, h_num, n_sweeps, n_discard) each; returns int64 [n, 6] records."""
+        """steps: (T, h_num, n_sweeps, n_discard[, hs_num]) each; returns int64 [n, 6] records."""
         n = len(steps)
         arr = make_steps(steps)
         out = (Record * max(1, n))()

@@ -465,3 +465,58 @@ def test_batched_whole_mode_rejects_bitpack(isf):
     lats[0].schedule_load([(2.0, 0, 2, 0)])
     with pytest.raises(IsfError):
         isf.Batch(1).advance(lats, 2, mode=2)
+
+
+# ------------------------------------------------------------------ switching-field gate (Eq. 9)
+GATED_STEPS = [(2.5, 30, 7, 0, 40), (0.8, -45, 4, 1, 160), (9.0, 0, 5, 2, -20), (3.0, -7, 6, 0, 0),
+               (1e-3, 241, 2, 0, 20), (1.5, 60, 66, 3, 7)]
+
+
+@pytest.mark.parametrize("kernel,tiling", [(0, (64, 4, 2)), (0, (16, 16, 1)), (1, (64, 4, 1)), (2, (32, 16, 8)),
+                                           (2, (16, 16, 4))])
+@pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1)])
+def test_gated_schedule_matches_oracle(isf, kernel, tiling, X, Y, Z):
+    h = _rand_h((Y, X), Z, 11 * X + Y + Z)
+    g, o = _pair(isf, h, Z, 97531, replica=8, init=2)
+    if kernel == 1:
+        g.attach_items()
+    g.set_tuning(tiling[0], tiling[1], tiling[2], X % 2 == 0, kernel)
+    _say("gated schedule", kernel, tiling, X, Y, Z)
+    np.testing.assert_array_equal(g.run_schedule(GATED_STEPS), np.array([o.run(*s).as_tuple() for s in GATED_STEPS]))
+    _assert_same(g, o)
+
+
+def test_gated_large_film_prefix(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.set_tuning(32, 32, 16, True, 2)
+    _say("gated large film prefix")
+    steps = [(c.T, hn, 5, 0, 40) for hn in (120, 60, 0, -60)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_gated_batch_equals_oracle(isf, mode):
+    films = _batch_films(isf)
+    films = [(h, Z, s, r, [st + ((40 * (i + 1)) % 170,) for st in sc])
+             for i, (h, Z, s, r, sc) in enumerate(films)]
+    lats = [isf.Lattice(h, Z, s, replica=r, init=2) for (h, Z, s, r, sc) in films]
+    _say("gated batch", mode)
+    recs = isf.Batch(len(lats)).run(lats, [f[4] for f in films], mode=mode)
+    for (h, Z, s, r, sc), lat, rec in zip(films, lats, recs):
+        o = cpu.Film(h, Z, s, r, init=2)
+        np.testing.assert_array_equal(rec, np.array([o.run(*st).as_tuple() for st in sc]))
+        np.testing.assert_array_equal(lat.spins(), o.spins())
+
+
+def test_gate_rejected_for_bitpacked_films(isf):
+    from paper_1205_5588_amd._lib import IsfError
+
+    g = isf.Lattice(_rand_h((16, 128), 3, 4), 3, 1, fmt=1)
+    with pytest.raises(IsfError):
+        g.run_schedule([(2.0, 0, 3, 0, 40)])
+    g.run_schedule([(2.0, 0, 3, 0, 0)])  # no gate: fine

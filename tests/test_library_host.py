@@ -99,3 +99,17 @@ def test_threshold_tables_equal_oracle(lib, oracle_lib):
     for T, h in pairs:
         assert lib.isf_threshold_table(float(T), int(h), out.ctypes.data) == 0
         np.testing.assert_array_equal(out, cpu.threshold_table(T, h), err_msg=str((T, h)))
+
+
+def test_gate_thresholds_equal_oracle(lib, oracle_lib):
+    """Switching-field gate thresholds (Eq. 9) of the library against the oracle's."""
+    import ctypes
+
+    out = ctypes.c_uint32()
+    for T in (1e-3, 0.5, 1.0, 2.0, 3.0, 4.0, 9.0, 12.0, 1e6):
+        for hs in (0, 1, -1, 7, 40, 80, 160, -160, 200000):
+            assert lib.isf_gate_threshold(float(T), int(hs), ctypes.byref(out)) == 0
+            assert out.value == cpu.gate_threshold(T, hs), (T, hs)
+    assert lib.isf_gate_threshold(1.0, 200001, ctypes.byref(out)) == -1
+    assert lib.isf_gate_threshold(0.0, 40, ctypes.byref(out)) == -1
+    assert lib.isf_gate_threshold(1.0, 40, None) == -1
