@@ -33,12 +33,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def plain_steps(cfg, first, count):
-    hs = cfg.h_nums
-    return [(cfg.T, hs[(first + i) % len(hs)], cfg.sweeps_per_step, 0) for i in range(count)]
+def plain_steps(cfg, first, count, hs_num=0):
+    hn = cfg.h_nums
+    return [(cfg.T, hn[(first + i) % len(hn)], cfg.sweeps_per_step, 0, hs_num) for i in range(count)]
 
 
-def bench_plain(cfg, h, fmt, steps, warmup, tuning=None):
+def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0):
     import torch
 
     from paper_1205_5588_amd.lattice import Lattice
@@ -50,13 +50,13 @@ def bench_plain(cfg, h, fmt, steps, warmup, tuning=None):
         lat.set_tuning(*tuning)
     n_occ = lat.observables()["n_occ"]
     if warmup:
-        lat.run_schedule(plain_steps(cfg, 0, warmup))
+        lat.run_schedule(plain_steps(cfg, 0, warmup, hs_num))
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(lat.stream)
-    recs = lat.run_schedule(plain_steps(cfg, warmup, steps))
+    recs = lat.run_schedule(plain_steps(cfg, warmup, steps, hs_num))
     ev1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -313,6 +313,14 @@ def main():
                             "tiling": None if tb is None else tb["tiling"]}
         log("bitpack:", extra["bitpack"])
         del lat_b
+        # the same ramp behind the switching-field gate of Eq. 9 with h_s = 2 (hs_num = 40)
+        lat_g, n_occ_g, sw_g, wall_g, gpu_ms_g, recs_g = bench_plain(cfg, h, 0, min(args.steps, 40), 2, tuning,
+                                                                     hs_num=40)
+        extra["gated"] = {"value": round(n_occ_g * sw_g / (gpu_ms_g * 1e-3), 1), "unit": "spin-flip attempts/s",
+                          "steps": min(args.steps, 40), "hs_num": 40,
+                          "accepted_per_attempt": round(float(recs_g[:, 5].sum()) / (n_occ_g * sw_g), 5)}
+        log("gated:", extra["gated"])
+        del lat_g
         extra["batched"] = bench_batched(args)
         log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
         if not args.no_serve:

@@ -51,6 +51,7 @@ def lib():
         L.orc_run_gated.restype = ctypes.c_int
         L.orc_gate_threshold.argtypes = [ctypes.c_int32, ctypes.c_double]
         L.orc_gate_threshold.restype = ctypes.c_uint32
+        L.orc_surface_image.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_get_spins.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_set_spins.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]
         L.orc_set_spins.restype = ctypes.c_int
@@ -136,6 +137,18 @@ class Film:
             raise ValueError("oracle: cube shape mismatch")
         if lib().orc_set_spins(self._p, cube.ctypes.data, int(t)) != 0:
             raise ValueError("oracle: occupied sites must hold +-1")
+
+    def surface_image(self) -> np.ndarray:
+        """Simulated PMOKE image [Y][X]: +1 / -1 = spin of the column's top occupied site, 0 = none."""
+        out = np.zeros((self.Y, self.X), dtype=np.int8)
+        lib().orc_surface_image(self._p, out.ctypes.data)
+        return out
+
+    def film_stats(self) -> dict:
+        """Mean coordination z = 2 N_bonds / N_occ and the critical concentration p_c = 2/z of Eq. (2)."""
+        _, _, n_occ, n_bonds, _ = self.state()
+        z = 2.0 * n_bonds / n_occ if n_occ else 0.0
+        return {"n_occ": n_occ, "n_bonds": n_bonds, "mean_coordination": z, "p_c": 2.0 / z if z else float("inf")}
 
     def state(self):
         """(M, E_bond, N_occ, N_bonds, sweeps done)."""

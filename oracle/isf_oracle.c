@@ -396,6 +396,24 @@ int orc_set_spins(orc_film *f, const int8_t *cube, uint64_t t)
     return 0;
 }
 
+/* Simulated PMOKE image (Section 6): only the surface atoms count, a white
+ * pixel (+1) for spin up and a black one (-1) for spin down.  The surface atom
+ * of column (x, y) is its occupied site with the largest z; a column without
+ * occupied sites gives the background (0).  img is [Y][X]. */
+void orc_surface_image(const orc_film *f, int8_t *img)
+{
+    for (int y = 0; y < f->Y; ++y)
+        for (int x = 0; x < f->X; ++x) {
+            int8_t v = 0;
+            for (int z = f->Z - 1; z >= 0; --z)
+                if (f->occ[cell(f, x, y, z)]) {
+                    v = f->s[cell(f, x, y, z)];
+                    break;
+                }
+            img[(size_t)y * f->X + x] = v;
+        }
+}
+
 void orc_state(const orc_film *f, int64_t out[5])
 {
     out[0] = f->M;

@@ -119,6 +119,20 @@ class TinyFilm:
         self.s = [1 if self.draw(i, 0, 1) < 0x80000000 else -1 for i in range(self.N)]
         self.t = 0
 
+    def surface_image(self) -> np.ndarray:
+        """PMOKE image from the site list: per column the site with the largest z."""
+        img = np.zeros((self.Y, self.X), dtype=np.int8)
+        top: Dict[Tuple[int, int], int] = {}
+        for i, (x, y, z) in enumerate(self.sites):
+            if (x, y) not in top or self.sites[top[(x, y)]][2] < z:
+                top[(x, y)] = i
+        for (x, y), i in top.items():
+            img[y, x] = self.s[i]
+        return img
+
+    def mean_coordination(self) -> float:
+        return 2.0 * len(self.bonds) / self.N if self.N else 0.0
+
     def magnetisation(self) -> int:
         return sum(self.s)
 

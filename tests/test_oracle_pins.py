@@ -518,3 +518,56 @@ def test_gated_exact_enumeration(oracle_lib):
     m = [f.run(T, hn, blk, 0, hs).sum_M / blk for _ in range(nblk)]
     se = float(np.std(m, ddof=1) / math.sqrt(nblk))
     assert abs(float(np.mean(m)) - ex["M"]) <= 5.0 * se + 1e-3
+
+
+# --------------------------------------------------------------------------- PMOKE image, mean coordination
+def _columns_with_a_site(h):
+    """Closed form: column (x, y) holds a site iff some z < h with z = x + y (mod 2), i.e.
+    h >= 2, or h == 1 and x + y even."""
+    Y, X = h.shape
+    parity = (np.add.outer(np.arange(Y), np.arange(X)) % 2) == 0
+    return (h >= 2) | ((h == 1) & parity)
+
+
+def test_surface_image_closed_forms(oracle_lib):
+    rng = np.random.default_rng(21)
+    for L in (1, 2, 3, 5):
+        h = np.full((12, 16), L, dtype=np.uint8)  # flat slab of L layers: full coordination 12 - 8/L
+        f = cpu.Film(h, L, seed=1, init=cpu.INIT_UP)
+        st = f.film_stats()
+        assert st["mean_coordination"] == pytest.approx(12.0 - 8.0 / L, abs=1e-12)
+        assert st["p_c"] == pytest.approx(2.0 / (12.0 - 8.0 / L), abs=1e-12)
+        img = f.surface_image()
+        # every column holds a site when L >= 2, the columns with x + y even when L == 1
+        np.testing.assert_array_equal(img, _columns_with_a_site(h).astype(np.int8))
+        assert (img != 0).mean() == (0.5 if L == 1 else 1.0)
+    h = rng.integers(0, 5, size=(20, 24)).astype(np.uint8)
+    for init in (cpu.INIT_UP, cpu.INIT_DOWN, cpu.INIT_RANDOM):
+        f = cpu.Film(h, 4, seed=5, init=init)
+        img = f.surface_image()
+        np.testing.assert_array_equal(img != 0, _columns_with_a_site(h))
+        if init == cpu.INIT_UP:
+            assert set(np.unique(img)) <= {0, 1}
+    # the image of the reversed state is the reversed image (H -> -H symmetry of the display)
+    f = cpu.Film(h, 4, seed=5, init=cpu.INIT_RANDOM)
+    f.run(2.5, 30, 3)
+    g = cpu.Film(h, 4, seed=5, init=cpu.INIT_RANDOM)
+    g.set_spins(-f.spins(), 3)
+    np.testing.assert_array_equal(g.surface_image(), -f.surface_image())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_surface_image_c_matches_python(oracle_lib, seed):
+    rng = np.random.default_rng(700 + seed)
+    Y, X, Z = [(8, 8, 3), (6, 10, 4), (10, 12, 5)][seed]
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    key = int(rng.integers(0, 2**63))
+    tf = ref.TinyFilm(h, Z, seed=key, replica=1)
+    tf.init_random()
+    cf = cpu.Film(h, Z, key, 1, init=cpu.INIT_RANDOM)
+    for T, hn in ((2.5, 20), (1.1, -7)):
+        for _ in range(3):
+            tf.sweep(T, hn)
+        cf.run(T, hn, 3)
+        np.testing.assert_array_equal(cf.surface_image(), tf.surface_image())
+    assert cf.film_stats()["mean_coordination"] == pytest.approx(tf.mean_coordination(), abs=1e-12)
