@@ -119,6 +119,24 @@ def lat_kernel_name(lat):
     return {KERNEL_LIST: "k_phase_i8_list", KERNEL_SWEEP: "k_sweep_i8_halo"}.get(t[4], "k_phase_i8")
 
 
+def bench_surface_image(lat, cfg, reps=20):
+    """Simulated PMOKE image of the film (one [Y][X] int8 image per call), timed with
+    HIP events on the film's stream."""
+    import torch
+
+    img = torch.empty(cfg.X * cfg.Y, dtype=torch.int8, device="cuda")
+    lat.surface_image(out=img)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(lat.stream)
+    for _ in range(reps):
+        lat.surface_image(out=img)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    return {"ms_per_image": round(ms, 5), "pixels_per_s": round(cfg.X * cfg.Y / (ms * 1e-3), 1)}
+
+
 def tune_plain(cfg, h, fmt):
     from paper_1205_5588_amd.autotune import tune_lattice
     from paper_1205_5588_amd.lattice import Lattice
@@ -297,11 +315,14 @@ def main():
     value = n_occ * sweeps / (gpu_ms * 1e-3)
     log("plain int8: %d steps, %d sweeps, %.3f s wall, %.3f ms gpu, %.3e attempts/s" %
         (args.steps, sweeps, wall, gpu_ms, value))
+    lat_stats = lat.film_stats()
     roof = roofline_int8(lat, cfg)
     log("roofline:", roof)
+    pmoke = bench_surface_image(lat, cfg)
+    log("pmoke image:", pmoke)
     del lat
 
-    extra = {"tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
+    extra = {"pmoke_image": pmoke, "film": lat_stats, "tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
                         "tuned": tune_info is not None,
                         "candidates": 0 if tune_info is None else len(tune_info["all"])}}
     if not args.no_extra:

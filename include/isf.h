@@ -187,6 +187,26 @@ int32_t isf_threshold_table(double T, int32_t h_num, uint32_t out[2][25]);
  * for T or |hs_num| out of range or a null output. */
 int32_t isf_gate_threshold(double T, int32_t hs_num, uint32_t *out);
 
+/* Simulated PMOKE image (Section 6): img_dev, a device buffer of at least
+ * X*Y bytes, receives [Y][X] int8 pixels: +1 (white) / -1 (black) = the spin of
+ * the column's surface atom, its occupied site with the largest z; 0 where
+ * the column holds no occupied site.  Enqueued on the lattice's stream after
+ * the sweeps already enqueued (asynchronous).  ENOSPC if bytes < X*Y. */
+int32_t isf_surface_image(isf_lattice *lat, int8_t *img_dev, uint64_t bytes);
+
+/* Film statistics from the exact counts: mean coordination z = 2 N_bonds /
+ * N_occ (nearest occupied neighbours per occupied site), the critical
+ * concentration p_c = 2/z of Eq. 2 (0 if z = 0) and the occupied fraction
+ * N_occ / (X Y Z / 2) of the stored sites.  Host-only, synchronous. */
+typedef struct {
+    int64_t n_occ;
+    int64_t n_bonds;
+    double mean_coordination;
+    double p_c;
+    double concentration;
+} isf_stats;
+int32_t isf_film_stats(const isf_lattice *lat, isf_stats *out);
+
 /* Occupied-dword lists (INT8 only).  Occupancy never changes, so for each
  * sublattice the dwords (4 compact sites) holding an occupied site can be
  * listed once; the list kernel then gives every block exactly the same number

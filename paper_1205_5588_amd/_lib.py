@@ -41,6 +41,11 @@ class Step(ctypes.Structure):
                 ("n_discard", ctypes.c_uint32), ("hs_num", ctypes.c_int32)]
 
 
+class FilmStats(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int64), ("n_bonds", ctypes.c_int64), ("mean_coordination", ctypes.c_double),
+                ("p_c", ctypes.c_double), ("concentration", ctypes.c_double)]
+
+
 class Obs(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("E", ctypes.c_int64), ("n_occ", ctypes.c_int64),
                 ("n_bonds", ctypes.c_int64), ("sweeps", ctypes.c_uint64)]
@@ -77,6 +82,8 @@ EXPORTS = {
     "isf_write_spins": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
     "isf_threshold_table": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]),
     "isf_gate_threshold": (ctypes.c_int32, [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32)]),
+    "isf_surface_image": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "isf_film_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "isf_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "isf_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "isf_schedule_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Step), ctypes.c_uint32]),

@@ -30,6 +30,7 @@ hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 const uint8_t *lists, uint32_t q, hipStream_t s);
 hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
+hipError_t launch_surface_image(const LatDev &L, const uint8_t *spins, int8_t *img, hipStream_t s);
 hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *begins, uint32_t n_ents,
                                       uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s);
 uint32_t halo_tiles(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t &nbx);
@@ -1066,6 +1067,39 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
     for (int s = 0; s < 4; ++s)
         ms[s] = n ? sum[s] / n : 0.0;
     *swept = n;
+    return ISF_OK;
+}
+
+int32_t isf_surface_image(isf_lattice *lat, int8_t *img_dev, uint64_t bytes) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!img_dev)
+        return fail(ISF_EINVAL, "null image buffer");
+    if (bytes < (uint64_t)lat->d.X * lat->d.Y)
+        return fail(ISF_ENOSPC, "image buffer of %llu bytes < X * Y = %llu", (unsigned long long)bytes,
+                    (unsigned long long)lat->d.X * lat->d.Y);
+    if ((rc = set_device_of(lat)))
+        return rc;
+    // the spins of the last enqueued sweep, whichever copy holds them
+    const uint8_t *cur = lat->cur_spare ? lat->spare : lat->L.spins;
+    hipError_t e = launch_surface_image(lat->L, cur, img_dev, lat->stream);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "surface image launch: %s", hipGetErrorString(e));
+    return ISF_OK;
+}
+
+int32_t isf_film_stats(const isf_lattice *lat, isf_stats *out) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(ISF_EINVAL, "null output");
+    out->n_occ = lat->n_occ;
+    out->n_bonds = lat->n_bonds;
+    out->mean_coordination = lat->n_occ ? 2.0 * (double)lat->n_bonds / (double)lat->n_occ : 0.0;
+    out->p_c = out->mean_coordination > 0.0 ? 2.0 / out->mean_coordination : 0.0;
+    out->concentration = (double)lat->n_occ / ((double)lat->d.X * lat->d.Y * lat->d.Z / 2.0);
     return ISF_OK;
 }
 

@@ -209,6 +209,26 @@ class Lattice:
         check(_lib.load().isf_recount(self.handle, ctypes.byref(M), ctypes.byref(E)))
         return int(M.value), int(E.value)
 
+    def surface_image(self, out=None) -> np.ndarray:
+        """Simulated PMOKE image [Y][X] int8 (+1 / -1 surface spin, 0 background) after the
+        sweeps enqueued so far.  out: optional int8 CUDA tensor of X*Y elements to fill."""
+        import torch
+
+        img = out if out is not None else torch.empty(self.Y * self.X, dtype=torch.int8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))  # the buffer's allocation
+        check(_lib.load().isf_surface_image(self.handle, img.data_ptr(), img.numel()))
+        if out is not None:
+            return out
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return img.view(self.Y, self.X).cpu().numpy()
+
+    def film_stats(self) -> dict:
+        """Mean coordination 2 N_bonds / N_occ, p_c = 2/z (Eq. 2) and the occupied fraction."""
+        st = _lib.FilmStats()
+        check(_lib.load().isf_film_stats(self.handle, ctypes.byref(st)))
+        return {"n_occ": st.n_occ, "n_bonds": st.n_bonds, "mean_coordination": st.mean_coordination,
+                "p_c": st.p_c, "concentration": st.concentration}
+
     def spins(self) -> np.ndarray:
         out = np.zeros((self.Z, self.Y, self.X), dtype=np.int8)
         check(_lib.load().isf_read_spins(self.handle, out.ctypes.data))

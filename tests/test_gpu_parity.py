@@ -520,3 +520,39 @@ def test_gate_rejected_for_bitpacked_films(isf):
     with pytest.raises(IsfError):
         g.run_schedule([(2.0, 0, 3, 0, 40)])
     g.run_schedule([(2.0, 0, 3, 0, 0)])  # no gate: fine
+
+
+# ------------------------------------------------------------------ PMOKE image and film statistics
+@pytest.mark.parametrize("fmt,kernel,tiling", [(0, 0, (64, 4, 2)), (0, 2, (32, 16, 8)), (1, 0, (64, 4, 1))])
+def test_surface_image_matches_oracle(isf, fmt, kernel, tiling):
+    X = 256 if fmt else 200
+    h = _rand_h((58, X), 6, 40 + fmt + kernel)
+    g, o = _pair(isf, h, 6, 1357, replica=2, init=2, fmt=fmt)
+    g.set_tuning(tiling[0], tiling[1], tiling[2], False, kernel)
+    _say("surface image", fmt, kernel)
+    np.testing.assert_array_equal(g.surface_image(), o.surface_image())
+    for hn, n in ((40, 3), (-60, 5), (0, 1)):  # odd sweep counts leave whole-sweep spins in the spare copy
+        g.run_sweeps(2.0, hn, n)
+        o.run(2.0, hn, n)
+        np.testing.assert_array_equal(g.surface_image(), o.surface_image(), err_msg=str(hn))
+    st, so = g.film_stats(), o.film_stats()
+    assert (st["n_occ"], st["n_bonds"]) == (so["n_occ"], so["n_bonds"])
+    assert st["mean_coordination"] == so["mean_coordination"] and st["p_c"] == so["p_c"]
+
+
+def test_surface_image_of_the_ramp_film(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.set_tuning(32, 32, 16, True, 2)
+    _say("surface image, large film")
+    g.ramp_field(c.T, [-120], 3)
+    o.run(c.T, -120, 3)
+    np.testing.assert_array_equal(g.surface_image(), o.surface_image())
+    with pytest.raises(Exception):
+        import torch
+
+        small = torch.empty(10, dtype=torch.int8, device="cuda")
+        g.surface_image(out=small)
