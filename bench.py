@@ -26,7 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_LIST, KERNEL_SWEEP = 1, 2  # isf_tuning.kernel
+KERNEL_LIST, KERNEL_SWEEP, KERNEL_PIPE = 1, 2, 3  # isf_tuning.kernel
 
 
 def log(*a):
@@ -84,7 +84,7 @@ def roofline_int8(lat, cfg, region_ms_per_sweep, n_sweeps=40):
     lat.schedule_load([(cfg.T, cfg.h_nums[0], n_sweeps, 0)])
     ms, n = lat.time_launches(n_sweeps)
     Nc = cfg.X * cfg.Y * cfg.Z // 2
-    if lat.get_tuning()[4] == KERNEL_SWEEP:
+    if lat.get_tuning()[4] in (KERNEL_SWEEP, KERNEL_PIPE):
         mean_ms, bytes_per_launch, min_bytes = region_ms_per_sweep, 5.0 * Nc, 2.0 * Nc
         ms = ms[:1]
     else:
@@ -124,7 +124,8 @@ def measured_traffic(kernel):
 
 def lat_kernel_name(lat):
     t = lat.get_tuning()
-    return {KERNEL_LIST: "k_phase_i8_list", KERNEL_SWEEP: "k_sweep_i8_halo"}.get(t[4], "k_phase_i8")
+    return {KERNEL_LIST: "k_phase_i8_list", KERNEL_SWEEP: "k_sweep_i8_halo",
+            KERNEL_PIPE: "k_sweep_i8_pipe"}.get(t[4], "k_phase_i8")
 
 
 def bench_surface_image(lat, cfg, reps=20):

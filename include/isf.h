@@ -110,16 +110,22 @@ typedef struct {
 } isf_obs;
 
 /* Launch shape of the sweep kernels.  Every shape gives the same trajectory. */
-enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1, ISF_KERNEL_SWEEP = 2 };
+enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1, ISF_KERNEL_SWEEP = 2, ISF_KERNEL_PIPE = 3 };
 typedef struct {
     uint32_t tile_x;    /* dwords (4 sites) per block row: 16, 32 or 64 */
     uint32_t tile_y;    /* TILES/LIST: active rows per block, tile_x * tile_y = 256;
-                           SWEEP: rows of the block's tile (16x16, 32x8, 32x16, 32x32, 64x8, 64x16) */
-    uint32_t rows_per_thread; /* 1, 2 or 4 (TILES); items per thread 1 or 2 (LIST); waves per block 4, 8 or 16 (SWEEP) */
+                           SWEEP: rows of the block's tile (16x16, 32x8, 32x16, 32x32, 64x8, 64x16);
+                           PIPE: 32x16, 32x32 or 64x16 */
+    uint32_t rows_per_thread; /* 1, 2 or 4 (TILES); items per thread 1 or 2 (LIST); waves per block 4, 8 or 16
+                                 (SWEEP); 8 or 16 (PIPE) */
     uint32_t use_graph; /* 1: replay schedules as HIP graphs, 0: plain launches */
     uint32_t kernel;    /* ISF_KERNEL_TILES; ISF_KERNEL_LIST (INT8 with items attached); ISF_KERNEL_SWEEP
                            (INT8: one launch per sweep, the block's tile and a halo in LDS; EINVAL if the
-                           shape's LDS for the film's Z exceeds the device's per-block limit) */
+                           shape's LDS for the film's Z exceeds the device's per-block limit); ISF_KERNEL_PIPE
+                           (INT8: one launch per sweep, one block per compute unit sweeping several tiles while
+                           the next tile's region streams into a second LDS buffer; EINVAL unless X is a
+                           multiple of 32, X/8 and Y are at least the region's width and height, and the
+                           double buffer fits the device's LDS) */
 } isf_tuning;
 
 typedef struct isf_lattice isf_lattice;

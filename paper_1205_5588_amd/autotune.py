@@ -20,7 +20,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, BATCH_WHOLE, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST,
-                   KERNEL_SWEEP, KERNEL_TILES, IsfError)
+                   KERNEL_PIPE, KERNEL_SWEEP, KERNEL_TILES, IsfError)
 
 TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
@@ -50,13 +50,13 @@ def default_tiling(X: int, fmt: int) -> Tuple[int, int, int]:
 def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
     """Heuristic (tile_x, tile_y, rows_or_waves, use_graph, kernel) for films not in the cache.
 
-    INT8 films whose planes fit the whole-sweep kernel's LDS take it (measured
-    fastest on MI355X for both the 512^2 x 5 and the 2048^2 x 8 films: large
-    tiles where the film is wide, 16 x 16 tiles on small films); others take
-    the sublattice tiles."""
+    INT8 films whose planes fit a whole-sweep kernel's LDS take one (measured
+    fastest on MI355X: the pipelined 32 x 32 kernel on wide films such as
+    2048^2 x 8, the single-tile kernel with 16 x 16 tiles on small films such
+    as 512^2 x 5); others take the sublattice tiles."""
     if fmt == FORMAT_INT8 and Z <= 8:
-        if X // 8 >= 256 and Y >= 512:
-            return (32, 32, 16, True, KERNEL_SWEEP)
+        if X // 8 >= 256 and Y >= 512 and X % 32 == 0:
+            return (32, 32, 16, True, KERNEL_PIPE)
         return (16, 16, 4, True, KERNEL_SWEEP)
     return default_tiling(X, fmt) + (True, KERNEL_TILES)
 
@@ -93,6 +93,9 @@ LIST_CANDIDATES = [(64, 4, 1, KERNEL_LIST), (64, 4, 2, KERNEL_LIST)]
 # does not fit the film's Z are skipped
 SWEEP_CANDIDATES = [(32, 16, 8, KERNEL_SWEEP), (16, 16, 4, KERNEL_SWEEP), (32, 8, 4, KERNEL_SWEEP),
                     (64, 8, 8, KERNEL_SWEEP), (32, 32, 8, KERNEL_SWEEP), (32, 32, 16, KERNEL_SWEEP)]
+# pipelined whole-sweep kernel (one block per compute unit, double-buffered LDS)
+PIPE_CANDIDATES = [(32, 16, 16, KERNEL_PIPE), (32, 16, 8, KERNEL_PIPE), (32, 32, 16, KERNEL_PIPE),
+                   (64, 16, 16, KERNEL_PIPE)]
 
 
 def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,
@@ -107,7 +110,7 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
 
     cands = [tuple(c) + ((KERNEL_TILES,) if len(c) == 3 else ()) for c in (candidates or TILINGS[fmt])]
     if fmt == FORMAT_INT8 and candidates is None:
-        cands += (LIST_CANDIDATES if lists else []) + SWEEP_CANDIDATES
+        cands += (LIST_CANDIDATES if lists else []) + SWEEP_CANDIDATES + PIPE_CANDIDATES
     ref_recs = ref_spins = None
     timings: List[dict] = []
     for tl in cands:

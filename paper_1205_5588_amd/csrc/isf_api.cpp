@@ -36,6 +36,13 @@ hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *be
 uint32_t halo_tiles(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t &nbx);
 hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s);
 hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
+uint32_t pipe_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
+uint32_t pipe_static_lds(uint32_t tx, uint32_t ty, uint32_t nt);
+uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
+uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
+hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
+hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
+                                const uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s);
 uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t halo_lists_bytes(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t Z);
@@ -124,7 +131,7 @@ uint64_t spin_bytes_of(const isf_desc *d) {
 
 // The aux buffer: device state, slots, schedule, tables and records, then (INT8)
 // the spare copy of the spins and the per-tile lists used by the whole-sweep
-// kernel (sized for the shape that needs the most).
+// kernels (sized for the shape that needs the most).
 uint64_t spare_offset() { return (aux_layout(ISF_MAX_STEPS).total + 4095) / 4096 * 4096; }
 
 uint64_t lists_offset(const isf_desc *d) { return (spare_offset() + spin_bytes_of(d) + 4095) / 4096 * 4096; }
@@ -132,8 +139,12 @@ uint64_t lists_offset(const isf_desc *d) { return (spare_offset() + spin_bytes_o
 uint64_t aux_bytes_of(const isf_desc *d) {
     if (d->format != ISF_FORMAT_INT8)
         return aux_layout(ISF_MAX_STEPS).total;
-    return lists_offset(d) + halo_lists_bytes_max(d->X / 8, d->Y, d->Z);
+    return lists_offset(d) + std::max(halo_lists_bytes_max(d->X / 8, d->Y, d->Z),
+                                      pipe_lists_bytes_max(d->X / 8, d->Y, d->Z));
 }
+
+// One launch per sweep (the single-tile or the pipelined whole-sweep kernel).
+bool is_whole(uint32_t kernel) { return kernel == ISF_KERNEL_SWEEP || kernel == ISF_KERNEL_PIPE; }
 
 // Threshold of Eq. (8) for an uphill move with dE = q/10: floor(2^32 exp(-dE/T)).
 uint32_t threshold_of(int32_t q, double T) {
@@ -172,6 +183,7 @@ struct isf_lattice {
     uint8_t *aux_dev;
     hipStream_t stream;
     int device;
+    uint32_t n_cu;  // compute units of the device
     Tiling tiling;
     bool use_graph;
     int64_t n_occ, n_bonds;
@@ -249,8 +261,9 @@ int32_t prepare_spare(isf_lattice *lat, const Tiling &tl) {
         lat->spare_ready = true;
     }
     const Tiling &lt = lat->lists_tiling;
-    if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty) {
-        hipError_t e = launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
+    if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty || lt.kernel != tl.kernel) {
+        hipError_t e = tl.kernel == ISF_KERNEL_PIPE ? launch_pipe_lists(lat->L, tl, lat->lists, lat->stream)
+                                                    : launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
         if (e != hipSuccess)
             return fail(ISF_EHIP, "list launch failed: %s", hipGetErrorString(e));
         lat->lists_ready = true;
@@ -296,8 +309,12 @@ int32_t settle(isf_lattice *lat) {
 // Sweep parity q = 1 when the current spins are in the spare copy.
 int32_t launch_whole_sweep(isf_lattice *lat) {
     uint8_t *a = lat->L.spins, *b = lat->spare;
-    hipError_t e = lat->cur_spare ? launch_sweep_i8_halo(lat->L, lat->tiling, b, a, lat->lists, 1, lat->stream)
-                                  : launch_sweep_i8_halo(lat->L, lat->tiling, a, b, lat->lists, 0, lat->stream);
+    const uint8_t *src = lat->cur_spare ? b : a;
+    uint8_t *dst = lat->cur_spare ? a : b;
+    const uint32_t q = lat->cur_spare ? 1u : 0u;
+    hipError_t e = lat->tiling.kernel == ISF_KERNEL_PIPE
+                       ? launch_sweep_i8_pipe(lat->L, lat->tiling, src, dst, lat->lists, q, lat->n_cu, lat->stream)
+                       : launch_sweep_i8_halo(lat->L, lat->tiling, src, dst, lat->lists, q, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     lat->cur_spare = !lat->cur_spare;
@@ -307,7 +324,7 @@ int32_t launch_whole_sweep(isf_lattice *lat) {
 // One sweep = one whole-sweep launch (its bookkeeping rides in the launch), or
 // four sublattice launches and the one-wave sweep-end launch.
 int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
-    const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
+    const bool whole = is_whole(lat->tiling.kernel);
     for (uint64_t i = 0; i < n; ++i) {
         if (whole) {
             int32_t rc = launch_whole_sweep(lat);
@@ -362,7 +379,7 @@ int32_t build_graph(isf_lattice *lat) {
 
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     int32_t rc0;
-    if (lat->tiling.kernel == ISF_KERNEL_SWEEP) {
+    if (is_whole(lat->tiling.kernel)) {
         if ((rc0 = prepare_spare(lat, lat->tiling)) || (rc0 = prime_whole(lat)))
             return rc0;
         // graphs hold an even number of whole sweeps and start from the main copy
@@ -545,10 +562,13 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     lat->stream = static_cast<hipStream_t>(stream);
     lat->tiling = Tiling{64, 4, 2, ISF_KERNEL_TILES};
     lat->use_graph = true;
-    if (hipGetDevice(&lat->device) != hipSuccess) {
+    int n_cu = 0;
+    if (hipGetDevice(&lat->device) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, lat->device) != hipSuccess) {
         delete lat;
         return fail(ISF_EHIP, "hipGetDevice failed");
     }
+    lat->n_cu = (uint32_t)std::max(n_cu, 1);
     LatDev &L = lat->L;
     L.spins = static_cast<uint8_t *>(spin_dev);
     lat->spare = d->format == ISF_FORMAT_INT8 ? lat->aux_dev + spare_offset() : nullptr;
@@ -625,6 +645,26 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
         if (lds > (uint32_t)max_lds - 1024u || halo_region_dwords(tl.tx, tl.ty, lat->d.Z) > 65536u)
             return fail(ISF_EINVAL, "whole-sweep shape %ux%u needs %u bytes of LDS for Z = %u (limit %d)", tl.tx,
                         tl.ty, lds, lat->d.Z, max_lds);
+    } else if (tl.kernel == ISF_KERNEL_PIPE) {
+        if (lat->d.format != ISF_FORMAT_INT8 || !lat->spare)
+            return fail(ISF_EINVAL, "the pipelined whole-sweep kernel needs an INT8 film");
+        const uint32_t nd = lat->d.X / 8, Y = lat->d.Y, Z = lat->d.Z;
+        const uint32_t lds = pipe_lds_bytes(tl.tx, tl.ty, Z);
+        if (lds == 0 || (tl.ry != 8 && tl.ry != 16))
+            return fail(ISF_EINVAL, "unsupported pipelined shape %ux%u with %u waves", tl.tx, tl.ty, tl.ry);
+        // 16-byte region pieces: rows of whole pieces, at least one region wide and high
+        if (nd % 4 != 0 || nd < tl.tx + 8 || Y < tl.ty + 8)
+            return fail(ISF_EINVAL, "pipelined shape %ux%u needs X a multiple of 32, X/8 >= %u and Y >= %u", tl.tx,
+                        tl.ty, tl.tx + 8, tl.ty + 8);
+        // compact dword indices below 2^31 (bit 31 flags the tile's rows) and plane offsets within 32 bits
+        if ((uint64_t)Z * Y * nd >= (1ull << 31) || (uint64_t)(Z + 2) * Y * nd * 4 >= (1ull << 32))
+            return fail(ISF_EINVAL, "film too large for the pipelined kernel");
+        int max_lds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
+        const uint64_t need = (uint64_t)lds + pipe_static_lds(tl.tx, tl.ty, 64u * tl.ry);
+        if (need > (uint64_t)max_lds || pipe_region_dwords(tl.tx, tl.ty, Z) > 65536u)
+            return fail(ISF_EINVAL, "pipelined shape %ux%u needs %llu bytes of LDS for Z = %u (limit %d)", tl.tx,
+                        tl.ty, (unsigned long long)need, Z, max_lds);
     } else if (tl.kernel != ISF_KERNEL_TILES) {
         return fail(ISF_EINVAL, "unknown kernel %u", tl.kernel);
     } else {
@@ -1029,7 +1069,7 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
     for (auto &e : ev)
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     int32_t status = ISF_OK;
-    const bool whole = lat->tiling.kernel == ISF_KERNEL_SWEEP;
+    const bool whole = is_whole(lat->tiling.kernel);
     if (whole ? ((rc = prepare_spare(lat, lat->tiling)) || (rc = prime_whole(lat))) : (rc = settle(lat)) != 0) {
         for (auto &e : ev)
             (void)hipEventDestroy(e);
@@ -1234,7 +1274,8 @@ int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
         if (lat->sched_total == lat->sched_enqueued)
             continue;
         const bool ready = lat->spare_ready && lat->lists_ready && lat->lists_tiling.tx == tl.tx &&
-                           lat->lists_tiling.ty == tl.ty && lat->whole_active;
+                           lat->lists_tiling.ty == tl.ty && lat->lists_tiling.kernel == tl.kernel &&
+                           lat->whole_active;
         if (ready)
             continue;
         int32_t rc;

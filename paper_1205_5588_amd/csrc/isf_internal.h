@@ -127,7 +127,7 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
 // Launch shape of the phase kernels.
 struct Tiling {
     uint32_t tx, ty, ry;  // threads along a row (dwords / words), threads across rows, rows per thread
-    uint32_t kernel;      // ISF_KERNEL_TILES or ISF_KERNEL_LIST (ry = list entries per thread)
+    uint32_t kernel;      // ISF_KERNEL_TILES, _LIST (ry = list entries per thread), _SWEEP or _PIPE (ry = waves)
 };
 
 // One film in a batched launch: its description and where its blocks start.

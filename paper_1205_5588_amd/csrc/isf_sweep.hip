@@ -243,6 +243,44 @@ __device__ __forceinline__ void book_advance(const LatDev &L, uint32_t cur, cons
             next_step != 0xFFFFFFFFu ? L.tables[(size_t)next_step * kTableWords + lane] : tab[lane];
 }
 
+// book_advance with its loads done in advance: cur_tab / next_tab hold word
+// `lane` of the current and of the next step's table, next_ns / next_nd the
+// next step's sweeps (valid where that step exists).
+__device__ __forceinline__ void book_advance_pre(const LatDev &L, uint32_t cur, const BookLds &bk, uint32_t cur_tab,
+                                                 uint32_t next_tab, uint32_t next_ns, uint32_t next_nd,
+                                                 uint32_t lane) {
+    uint32_t changed = 0;
+    if (lane == 0) {
+        uint32_t step = bk.w[10], sis = bk.w[11], ns = bk.w[12], nd = bk.w[13], run = bk.w[14];
+        const uint32_t n_steps = bk.w[33];
+        if (run) {
+            if (++sis >= ns) {
+                ++step;
+                sis = 0;
+                run = step < n_steps;
+                if (run) {
+                    ns = next_ns;
+                    nd = next_nd;
+                    changed = 1;
+                }
+            }
+        }
+        const uint32_t ran = bk.w[14];  // see book_advance: a launch past the schedule is no sweep
+        SweepPos &np = L.pos[1 - cur];
+        np.t = (uint64_t)w64(bk, 8) + ran;
+        np.step = step;
+        np.sis = sis;
+        np.n_sweeps = ns;
+        np.n_discard = nd;
+        np.run = run;
+        np.pending = 0;
+        L.pos[cur].pending = ran;
+    }
+    changed = __shfl(changed, 0, 64);
+    if (lane < kTableWords)
+        L.pos[1 - cur].table[lane] = changed ? next_tab : cur_tab;
+}
+
 }  // namespace
 
 // Start of a run of whole-sweep launches: the position of the first sweep
@@ -639,6 +677,413 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo_batch(const WholeEntry *__
                              q);
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined whole sweep: one block per compute unit works through several
+// tiles of the same sweep, and while it runs the four phases of one tile the
+// region and lists of its next tile stream from HBM straight into the other
+// half of a double buffer in LDS (global-to-LDS loads, which hold no
+// registers), so the load of every tile but the first hides behind compute.
+// The phases, draws and acceptance are those of the single-tile kernel above;
+// only the data movement differs:
+//   * the halo is 4 dwords wide along x, so that every region row starts on a
+//     16-byte boundary and moves as 16-byte pieces that never straddle the
+//     periodic seam (rows of the film must hold a multiple of 4 dwords);
+//   * the two region buffers share their padding planes: buffer 0 spans
+//     planes 0 .. Z+1 and buffer 1 planes Z+1 .. 2Z+2 of one array;
+//   * a tile's HBM record packs its four lists (each padded to 8 entries,
+//     one 16-byte piece) behind the four counts, so a tile moves exactly its
+//     occupied dwords' entries;
+//   * a tile's write-back is issued after the next tile's loads are known
+//     to have landed, so waiting for one never waits for the other.
+constexpr int kPX = 4;  // halo dwords on each side along x (pipelined kernel)
+
+template <int TXD, int TYR>
+struct GeoP {
+    static constexpr int RX = TXD + 2 * kPX;
+    static constexpr int RYN = TYR + 2 * kHY;
+    static constexpr int PL = RX * RYN;
+    static constexpr int CH = RX / 4;  // 16-byte pieces per region row
+    static_assert(TXD % 4 == 0, "tile rows must be whole 16-byte pieces");
+    __host__ __device__ static constexpr int lo(int s) { return kHY - (3 - s); }
+    __host__ __device__ static constexpr int hi(int s) { return kHY + TYR + (3 - s); }
+    __host__ __device__ static constexpr int r0(int s) { return lo(s) + ((lo(s) ^ (s & 1)) & 1); }
+    __host__ __device__ static constexpr int nry(int s) { return (hi(s) - r0(s) + 1) / 2; }
+    __host__ __device__ static constexpr int cx0(int s) { return s < 3 ? kPX - 1 : kPX; }
+    __host__ __device__ static constexpr int ncx(int s) { return s < 3 ? TXD + 2 : TXD; }
+    __host__ __device__ static constexpr uint32_t nz(int s, uint32_t Z) { return (Z - (uint32_t)(s >> 1) + 1) / 2; }
+    __host__ __device__ static constexpr uint32_t cand(int s, uint32_t Z) {
+        return (uint32_t)(nry(s) * ncx(s)) * nz(s, Z);
+    }
+    // most 16-byte pieces of a record: the counts, then each list padded to 8 entries
+    __host__ __device__ static constexpr uint32_t cap_pieces(uint32_t Z) {
+        return 1u + (cand(0, Z) + 7u) / 8u + (cand(1, Z) + 7u) / 8u + (cand(2, Z) + 7u) / 8u + (cand(3, Z) + 7u) / 8u;
+    }
+    __host__ __device__ static constexpr uint32_t rec_bytes(uint32_t Z) { return (16u * cap_pieces(Z) + 255u) & ~255u; }
+    // LDS: regions [2Z+3 planes] | lists of buffer 0 | lists of buffer 1 | row table | dword table
+    __host__ __device__ static constexpr uint32_t region_words(uint32_t Z) { return (2u * Z + 3u) * PL; }
+    __host__ __device__ static constexpr uint32_t list_bytes(uint32_t Z) { return 16u * cap_pieces(Z); }
+    __host__ __device__ static constexpr uint32_t off_lists(uint32_t Z) { return 4u * region_words(Z); }
+    __host__ __device__ static constexpr uint32_t off_rowk(uint32_t Z) { return off_lists(Z) + 2u * list_bytes(Z); }
+    __host__ __device__ static constexpr uint32_t off_dmap(uint32_t Z) { return off_rowk(Z) + 4u * (Z + 2) * RYN; }
+    __host__ __device__ static constexpr uint32_t lds_bytes(uint32_t Z) { return off_dmap(Z) + 4u * RX; }
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(3))) uint32_t lds_u32_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// 16 bytes per lane from HBM into LDS: lane l's piece lands at lds_wave + 16 l
+// (lds_wave is the same for the whole wave).  Completion is counted like any
+// vector load; the data may be read after s_waitcnt vmcnt(0) and a barrier.
+__device__ __forceinline__ void load_to_lds16(const void *g, void *lds_wave) {
+    __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_wave, 16, 0, 0);
+}
+
+// Workgroup barrier for LDS data only.  __syncthreads() also waits for every
+// vector memory operation in flight, the loads into the other LDS buffer
+// included; between the phases only this block's LDS writes must be done.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left alone
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Lists of the pipelined kernel: per tile the four counts, then the four lists
+// packed (each padded to a multiple of 8 entries).  One block per tile; a
+// counting pass fixes the offsets, a second pass writes the entries.
+template <int TXD, int TYR>
+__global__ __launch_bounds__(256) void k_pipe_lists(LatDev L, uint32_t nbx, uint8_t *lists) {
+    using G = GeoP<TXD, TYR>;
+    __shared__ uint32_t cnt[4], pos[4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t Y = L.Y, Z = L.Z, nd = L.nd;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t bx = tile % nbx, by = tile / nbx;
+    const int d0 = (int)(bx * TXD), y0 = (int)(by * TYR);
+    uint8_t *rec = lists + (size_t)tile * G::rec_bytes(Z);
+    uint16_t *ent = reinterpret_cast<uint16_t *>(rec);
+    if (tid < 4) {
+        cnt[tid] = 0;
+        pos[tid] = 0;
+    }
+    __syncthreads();
+    const char *spins = reinterpret_cast<const char *>(L.spins);
+    const size_t rowb = (size_t)nd * 4u, planeb = (size_t)Y * rowb;
+    for (int pass = 0; pass < 2; ++pass) {
+        uint32_t base_e = 8;  // list s starts after the counts and the padded lists before it
+        for (int s = 0; s < 4; ++s) {
+            const uint32_t n = G::cand(s, Z);
+            const uint32_t nr = (n + 255u) / 256u * 256u;
+            for (uint32_t c = tid; c < nr; c += 256) {
+                uint32_t ri = 0;
+                bool occ = false;
+                if (c < n) {
+                    const uint32_t cx = G::cx0(s) + c % G::ncx(s);
+                    const uint32_t q = c / G::ncx(s);
+                    const uint32_t ry = G::r0(s) + 2 * (q % G::nry(s));
+                    const uint32_t z = (uint32_t)(s >> 1) + 2 * (q / G::nry(s));
+                    ri = ((z + 1) * G::RYN + ry) * G::RX + cx;
+                    const int y = wrap_mod(y0 - kHY + (int)ry, (int)Y), d = wrap_mod(d0 - kPX + (int)cx, (int)nd);
+                    const uint32_t v = *reinterpret_cast<const uint32_t *>(spins + (z + 1) * planeb +
+                                                                           (size_t)y * rowb + (size_t)d * 4u);
+                    occ = v != kVacant;
+                }
+                const uint64_t m = __ballot(occ);
+                if (m) {
+                    const uint32_t at =
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    uint32_t b0 = 0;
+                    if (lane == 0)
+                        b0 = atomicAdd(pass == 0 ? &cnt[s] : &pos[s], (uint32_t)__popcll(m));
+                    b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active here
+                    if (pass == 1 && occ)
+                        ent[base_e + b0 + at] = (uint16_t)ri;
+                }
+            }
+            if (pass == 1)
+                base_e += (cnt[s] + 7u) & ~7u;
+        }
+        __syncthreads();
+    }
+    if (tid < 4)
+        reinterpret_cast<uint32_t *>(rec)[tid] = cnt[tid];
+}
+
+// One attempt on the dword at region index qi in phase S of the pipelined
+// kernel.  tab64 holds the thresholds at n + 12 + 32 [s = +1], so the key of
+// four sites is one shift and OR of their neighbour sums.  (Two dwords per
+// iteration, interleaved, measured slower here: the register pressure costs
+// more than the overlap gains.)
+template <int S, int RX, int PL>
+__device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const uint32_t *rowk, const uint32_t *dmap,
+                                             const uint32_t *tab64, uint32_t gthr, uint32_t t, const LatDev &L,
+                                             int &dM, int &dE, int &acc) {
+    constexpr bool kLeft = ((S & 1) ^ (S >> 1)) == 0;  // (y + z) even: the shifted columns are j - 1
+    constexpr int kB = PL + RX;                        // offset of the dword from its gather base
+    constexpr int o = kLeft ? -1 : 1;
+    auto sh = [](uint32_t cur, uint32_t other) {
+        return kLeft ? __builtin_amdgcn_alignbyte(cur, other, 3) : __builtin_amdgcn_alignbyte(other, cur, 1);
+    };
+    const uint32_t row = qi / RX, cx = qi - row * RX;
+    const uint32_t rk = rowk[row], dm = dmap[cx];
+    // gather base at the lowest neighbour: every offset below is a non-negative
+    // immediate (the empty asm keeps the compiler from folding it back; the
+    // pointer is an LDS one so that the reads stay LDS reads)
+    const lds_u32_t *Rg = (const lds_u32_t *)(Rb + (qi - kB));
+    asm volatile("" : "+v"(Rg));
+    const uint32_t a = Rg[kB];
+    const uint32_t a1 = Rg[kB - RX], a2 = Rg[kB + RX];
+    const uint32_t b1 = Rg[kB - PL], b2 = Rg[kB + PL];
+    const uint32_t a1o = Rg[kB - RX + o], a2o = Rg[kB + RX + o];
+    const uint32_t b1o = Rg[kB - PL + o], b2o = Rg[kB + PL + o];
+    const uint32_t e1 = Rg[0], e2 = Rg[kB - PL + RX];
+    const uint32_t e3 = Rg[kB + PL - RX], e4 = Rg[kB + PL + RX];
+    const uint32_t sum = (a1 + a2) + (b1 + b2) + ((sh(a1, a1o) + sh(a2, a2o)) + (sh(b1, b1o) + sh(b2, b2o))) +
+                         ((e1 + e2) + (e3 + e4));
+    const uint32_t site4 = (rk & 0x7FFFFFFFu) + (dm & 0x7FFFFFFFu);
+    uint32_t u[4];
+    philox(site4, t, L.replica, (uint32_t)S, L.key0, L.key1, u);
+    const uint32_t key = sum | (((a >> 1) & 0x01010101u) << 5);  // n + 12 + 32 [s = +1] <= 56
+    uint32_t f = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // exact single test: see the acceptance note of the single-tile kernel
+        const uint32_t thr = tab64[(key >> (8 * j)) & 0xFFu];
+        f |= (min(u[j], 0xFFFFFFFEu) < thr) ? (2u << (8 * j)) : 0u;
+    }
+    f &= (~a & 0x01010101u) << 1;  // vacancies never flip
+    if (f)
+        f &= gate_mask(gthr, site4, t, L.replica, (uint32_t)S, L.key0, L.key1);
+    if (f) {
+        Rb[qi] = a ^ f;
+        if ((rk & dm) >> 31) {  // a dword of this block's tile
+            const uint32_t fu = f & a, fd = f ^ fu;
+            const int cu = __popc(fu), cd = __popc(fd);
+            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            dM += 2 * (cd - cu);
+            dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
+            acc += cu + cd;
+        }
+    }
+}
+
+// All dwords of phase S listed in ls[0 .. n), one per thread and iteration.
+template <int S, int RX, int PL, int NT>
+__device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint32_t *Rb, const uint32_t *rowk,
+                                           const uint32_t *dmap, const uint32_t *tab64, uint32_t gthr, uint32_t t,
+                                           const LatDev &L, int &dM, int &dE, int &acc) {
+    for (uint32_t i = threadIdx.x; i < n; i += NT)
+        pipe_attempt<S, RX, PL>(ls[i], Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+}
+
+// The books of the pipelined kernel: as book_advance, with everything it reads
+// loaded when the block starts (the next step's descriptor and thresholds, the
+// current thresholds), so that the block's end waits for no memory.
+struct BookNext {
+    uint32_t tab;         // lane < kTableWords: word `lane` of the next sweep's table
+    uint32_t ns, nd, ok;  // the next step's sweeps and discarded sweeps; ok: that step exists
+};
+
+// Issued by the book-keeping wave once bk holds this sweep's position (its step
+// in word 10) and the film's step count (word 33).
+__device__ __forceinline__ BookNext book_next_issue(const LatDev &L, const BookLds &bk, uint32_t lane) {
+    BookNext b;
+    const uint32_t step = bk.w[10], n_steps = bk.w[33];
+    b.ok = step + 1 < n_steps;
+    b.ns = b.ok ? L.steps[step + 1].n_sweeps : 0u;
+    b.nd = b.ok ? L.steps[step + 1].n_discard : 0u;
+    b.tab = b.ok && lane < kTableWords ? L.tables[(size_t)(step + 1) * kTableWords + lane] : 0u;
+    return b;
+}
+
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *__restrict__ src,
+                                                      uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
+                                                      uint32_t nbx, uint32_t ntiles, uint32_t q) {
+    using G = GeoP<TXD, TYR>;
+    constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL, CH = G::CH;
+    extern __shared__ __align__(16) uint8_t smb[];
+    __shared__ uint32_t tab64[64];  // thresholds at n + 12 + 32 [s = +1]
+    __shared__ uint32_t gthr_sh, t_sh, run_sh;
+    __shared__ BookLds bk;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // the wave's index, in a scalar register
+    const uint32_t Y = L.Y, Z = L.Z, nd = L.nd;
+    const uint32_t np = Z + 2;
+    uint32_t *R = reinterpret_cast<uint32_t *>(smb);
+    uint8_t *LB = smb + G::off_lists(Z);
+    uint32_t *rowk = reinterpret_cast<uint32_t *>(smb + G::off_rowk(Z));  // Philox base | tile-row flag (bit 31)
+    uint32_t *dmap = reinterpret_cast<uint32_t *>(smb + G::off_dmap(Z));  // film dword | tile-dword flag (bit 31)
+    const uint32_t rowb = nd * 4u;
+    const uint32_t planeb = Y * rowb;  // the host checks that (Z + 2) planes fit 32-bit offsets
+    const uint32_t recb = G::rec_bytes(Z);
+
+    // This block's tiles: block b sits on XCD b % 8, which works through the
+    // band of tiles [x * per_xcd, (x + 1) * per_xcd); its blocks take every
+    // (grid / 8)-th tile of the band, so at any moment an XCD works on a
+    // contiguous run of tiles whose halos overlap in its L2.
+    const uint32_t xcd = blockIdx.x & 7u, gb = gridDim.x >> 3;
+    const uint32_t per_xcd = (ntiles + 7u) / 8u;
+    const uint32_t t_first = xcd * per_xcd + (blockIdx.x >> 3);
+    const uint32_t t_end = min((xcd + 1u) * per_xcd, ntiles);
+
+    // Issue the loads of a tile's planes 1..Z and of its whole list record
+    // (at capacity: its length would be one more memory round trip) into
+    // buffer buf.
+    // A wave's load moves up to kRowsPerLoad whole region rows of one plane (CH
+    // pieces each, the other lanes idle): a lane's column piece is fixed, the
+    // plane is the same for the whole wave, and only the row varies by lane.
+    constexpr uint32_t kRowsPerLoad = 64 / CH;
+    constexpr uint32_t kLoadsPerPlane = (RYN + kRowsPerLoad - 1) / kRowsPerLoad;
+    const uint32_t lrow = lane / CH, lcol = lane - lrow * CH;
+    auto issue = [&](uint32_t tile, uint32_t buf) {
+        const uint32_t bx = tile % nbx, by = tile / nbx;
+        int d = (int)(bx * TXD) - kPX + 4 * (int)lcol;  // within one period of the row (nd >= RX)
+        d += d < 0 ? (int)nd : 0;
+        d -= d >= (int)nd ? (int)nd : 0;
+        const char *col = reinterpret_cast<const char *>(src) + planeb + (uint32_t)d * 4u;  // plane 1
+        const int ry0 = (int)(by * TYR) - kHY;
+        uint32_t *Rb = R + (buf * (Z + 1) + 1) * PL;  // plane 1 of the buffer
+        for (uint32_t ld = wv; ld < Z * kLoadsPerPlane; ld += NT / 64) {  // uniform
+            const uint32_t p = ld / kLoadsPerPlane, r0 = (ld - p * kLoadsPerPlane) * kRowsPerLoad;
+            const uint32_t ry = r0 + lrow;
+            if (lrow < kRowsPerLoad && ry < (uint32_t)RYN) {
+                int y = ry0 + (int)ry;  // within one period of the film (Y >= RYN)
+                y += y < 0 ? (int)Y : 0;
+                y -= y >= (int)Y ? (int)Y : 0;
+                load_to_lds16(col + (p * planeb + (uint32_t)y * rowb), Rb + (p * RYN + r0) * RX);
+            }
+        }
+        const uint8_t *rec = lists + (size_t)tile * recb;
+        uint8_t *lb = LB + buf * G::list_bytes(Z);
+        const uint32_t pieces = G::cap_pieces(Z);
+        for (uint32_t k0 = wv * 64u; k0 < pieces; k0 += NT) {
+            const uint32_t k = k0 + lane;
+            if (k < pieces)
+                load_to_lds16(rec + 16u * k, lb + 16u * k0);
+        }
+    };
+
+    // padding planes (vacancies): 0, Z + 1 (shared by the buffers) and 2Z + 2
+    constexpr uint32_t PL4 = PL / 4;
+    for (uint32_t i = tid; i < 3u * PL4; i += NT)
+        reinterpret_cast<uint4 *>(R + (i / PL4) * (Z + 1) * PL)[i % PL4] = make_uint4(kVacant, kVacant, kVacant, kVacant);
+    if (t_first < t_end)
+        issue(t_first, 0);
+    const bool booker = blockIdx.x == 0 && tid < 64;  // block 0 holds tile 0 and keeps the books
+    BookRegs br;
+    uint32_t cur_tab = 0;
+    if (booker) {
+        br = book_issue(L, 1 - q, q, tid);
+        cur_tab = tid < kTableWords ? L.pos[q].table[tid] : 0u;
+    }
+    const SweepPos &P = L.pos[q];
+    if (tid < 64) {
+        const uint32_t up = tid >> 5, m = tid & 31u;
+        tab64[tid] = m < 25u ? P.table[25u * up + m] : 0u;
+    }
+    if (tid == 0) {
+        gthr_sh = P.table[kGateWord];
+        t_sh = (uint32_t)P.t;
+        run_sh = P.run;
+    }
+
+    int dM = 0, dE = 0, acc = 0;
+    uint32_t prev = 0xFFFFFFFFu;
+    char *out = reinterpret_cast<char *>(dst);
+    // Write tile `tile` (in buffer buf) back: its 16-byte pieces that hold an
+    // occupied site.  A thread keeps one piece column and row of the tile and
+    // steps through the planes.
+    constexpr uint32_t TX4 = TXD / 4, kPiecesPerPlane = TX4 * TYR, kPlaneStep = NT / kPiecesPerPlane;
+    static_assert(NT % kPiecesPerPlane == 0, "a block covers whole planes of a tile");
+    const uint32_t wb_cx = 4 * (tid % TX4), wb_ry = (tid / TX4) % TYR, wb_p0 = tid / kPiecesPerPlane + 1;
+    auto write_back = [&](uint32_t tile, uint32_t buf) {
+        const uint32_t bx = tile % nbx, by = tile / nbx;
+        const uint32_t y = by * TYR + wb_ry, d = bx * TXD + wb_cx;
+        if (y >= Y || d >= nd)  // a ragged tile's part beyond the film
+            return;
+        const uint32_t *from = R + buf * (Z + 1) * PL + (wb_p0 * RYN + wb_ry + kHY) * RX + wb_cx + kPX;
+        char *to = out + (wb_p0 * planeb + y * rowb + d * 4u);
+        for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(from);
+            if (v.x != kVacant || v.y != kVacant || v.z != kVacant || v.w != kVacant)
+                *reinterpret_cast<uint4 *>(to) = v;
+        }
+    };
+
+    BookNext bn{};
+    uint32_t k = 0;
+    for (uint32_t tile = t_first; tile < t_end; tile += gb, ++k) {
+        const uint32_t buf = k & 1u;
+        // this tile's loads (and the write-back of two tiles ago) have landed
+        __builtin_amdgcn_s_waitcnt(0);
+        if (prev != 0xFFFFFFFFu)
+            write_back(prev, buf ^ 1u);
+        const uint32_t bx = tile % nbx, by = tile / nbx;
+        const int d0 = (int)(bx * TXD), y0 = (int)(by * TYR);
+        const uint32_t ynd = Y * nd;
+        for (uint32_t i = tid; i < np * RYN + RX; i += NT) {
+            if (i < np * RYN) {
+                const uint32_t p = i / RYN, ry = i % RYN;
+                int y = y0 + (int)ry - kHY;  // within one period of the film (Y >= RYN)
+                y += y < 0 ? (int)Y : 0;
+                y -= y >= (int)Y ? (int)Y : 0;
+                const bool own = ry >= (uint32_t)kHY && ry < (uint32_t)(kHY + TYR) && y0 + (int)ry - kHY < (int)Y;
+                rowk[i] = (p >= 1 ? (p - 1) * ynd + (uint32_t)y * nd : 0u) | (own ? 0x80000000u : 0u);
+            } else {
+                const uint32_t c = i - np * RYN;
+                int d = d0 + (int)c - kPX;  // within one period of the row (nd >= RX)
+                d += d < 0 ? (int)nd : 0;
+                d -= d >= (int)nd ? (int)nd : 0;
+                const bool own = c >= (uint32_t)kPX && c < (uint32_t)(kPX + TXD) && d0 + (int)c - kPX < (int)nd;
+                dmap[c] = (uint32_t)d | (own ? 0x80000000u : 0u);
+            }
+        }
+        if (booker && k == 0) {
+            book_stage(bk, br, tid);
+            bn = book_next_issue(L, bk, tid);  // lands while the tiles are swept
+        }
+        __syncthreads();
+        const uint16_t *lb = reinterpret_cast<const uint16_t *>(LB + buf * G::list_bytes(Z));
+        // the counts are read before the next tile's loads are issued: a read
+        // of LDS behind those loads would wait for them
+        const uint4 cnt = *reinterpret_cast<const uint4 *>(lb);
+        // the next tile streams into the other buffer while this one is swept
+        if (tile + gb < t_end)
+            issue(tile + gb, buf ^ 1u);
+        prev = tile;
+        if (!run_sh) {  // uniform: the schedule is finished; nothing flips
+            lds_barrier();
+            continue;
+        }
+        uint32_t *Rb = R + buf * (Z + 1) * PL;
+        const uint32_t t = t_sh, gthr = gthr_sh;
+        const uint32_t l1 = 8u + ((cnt.x + 7u) & ~7u), l2 = l1 + ((cnt.y + 7u) & ~7u), l3 = l2 + ((cnt.z + 7u) & ~7u);
+        pipe_phase<0, RX, PL, NT>(lb + 8, cnt.x, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        lds_barrier();
+        pipe_phase<1, RX, PL, NT>(lb + l1, cnt.y, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        lds_barrier();
+        pipe_phase<2, RX, PL, NT>(lb + l2, cnt.z, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        lds_barrier();
+        pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        lds_barrier();
+    }
+    if (prev != 0xFFFFFFFFu)
+        write_back(prev, (k - 1u) & 1u);
+    if (k == 0 && booker) {  // a block without tiles (not block 0: it always holds tile 0)
+        book_stage(bk, br, tid);
+        bn = book_next_issue(L, bk, tid);
+    }
+    finish_block_to<NT>(slots_of(L, q), dM, dE, acc, blockIdx.x);
+    if (booker) {
+        book_fold(L, 1 - q, bk, tid);
+        book_advance_pre(L, q, bk, cur_tab, bn.tab, bn.ns, bn.nd, tid);
+    }
+}
+
 namespace {
 
 template <int TXD, int TYR>
@@ -695,6 +1140,50 @@ template <int TXD, int TYR>
 uint64_t lists_bytes_t(uint32_t nd, uint32_t Y, uint32_t Z) {
     const uint64_t tiles = (uint64_t)((nd + TXD - 1) / TXD) * ((Y + TYR - 1) / TYR);
     return tiles * Geo<TXD, TYR>::rec_bytes(Z);
+}
+
+template <int TXD, int TYR>
+void pipe_grid_of(const LatDev &L, uint32_t n_cu, uint32_t &nbx, uint32_t &tiles, uint32_t &blocks) {
+    nbx = (L.nd + TXD - 1) / TXD;
+    tiles = nbx * ((L.Y + TYR - 1) / TYR);
+    const uint32_t per_xcd = (tiles + 7) / 8;
+    blocks = 8u * std::max(1u, std::min((n_cu + 7) / 8, per_xcd));  // one block per compute unit at most
+}
+
+template <int TXD, int TYR>
+hipError_t launch_pipe_t(const LatDev &L, const uint8_t *src, uint8_t *dst, const uint8_t *lists, uint32_t nt,
+                         uint32_t q, uint32_t n_cu, hipStream_t s) {
+    uint32_t nbx, tiles, blocks;
+    pipe_grid_of<TXD, TYR>(L, n_cu, nbx, tiles, blocks);
+    const size_t lds = GeoP<TXD, TYR>::lds_bytes(L.Z);
+    if (nt == 1024)
+        hipLaunchKernelGGL((k_sweep_i8_pipe<TXD, TYR, 1024>), dim3(blocks), dim3(1024), lds, s, L, src, dst, lists,
+                           nbx, tiles, q);
+    else
+        hipLaunchKernelGGL((k_sweep_i8_pipe<TXD, TYR, 512>), dim3(blocks), dim3(512), lds, s, L, src, dst, lists,
+                           nbx, tiles, q);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+uint32_t pipe_static_lds_t(uint32_t nt) {
+    hipFuncAttributes a{};
+    const hipError_t e = nt == 1024 ? hipFuncGetAttributes(&a, (const void *)k_sweep_i8_pipe<TXD, TYR, 1024>)
+                                    : hipFuncGetAttributes(&a, (const void *)k_sweep_i8_pipe<TXD, TYR, 512>);
+    return e == hipSuccess ? (uint32_t)a.sharedSizeBytes : 0xFFFFFFFFu;
+}
+
+template <int TXD, int TYR>
+hipError_t launch_pipe_lists_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
+    const uint32_t nbx = (L.nd + TXD - 1) / TXD, tiles = nbx * ((L.Y + TYR - 1) / TYR);
+    hipLaunchKernelGGL((k_pipe_lists<TXD, TYR>), dim3(tiles), dim3(256), 0, s, L, nbx, lists);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+uint64_t pipe_lists_bytes_t(uint32_t nd, uint32_t Y, uint32_t Z) {
+    const uint64_t tiles = (uint64_t)((nd + TXD - 1) / TXD) * ((Y + TYR - 1) / TYR);
+    return tiles * GeoP<TXD, TYR>::rec_bytes(Z);
 }
 
 }  // namespace
@@ -789,6 +1278,66 @@ hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *be
     if (tl.tx == A && tl.ty == B) \
         return launch_halo_batch_t<A, B>(ents, begins, n_ents, blocks, Zmax, nt, g, s);
     ISF_HALO_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
+}
+
+#define ISF_PIPE_SHAPES(X) X(32, 16) X(32, 32) X(64, 16)
+
+// Pipelined whole-sweep kernel: dynamic LDS bytes for a film of Z planes (0 if
+// (tile_x, tile_y) is not a compiled shape), its static LDS, region dwords
+// (list entries are 16-bit region indices) and list bytes.
+uint32_t pipe_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z) {
+#define ISF_CASE(A, B) \
+    if (tx == A && ty == B) \
+        return GeoP<A, B>::lds_bytes(Z);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return 0;
+}
+
+uint32_t pipe_static_lds(uint32_t tx, uint32_t ty, uint32_t nt) {
+#define ISF_CASE(A, B) \
+    if (tx == A && ty == B) \
+        return pipe_static_lds_t<A, B>(nt);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return 0xFFFFFFFFu;
+}
+
+uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z) {
+    return (Z + 2) * (tx + 2 * kPX) * (ty + 2 * kHY);
+}
+
+uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z) {
+    uint64_t m = 0;
+#define ISF_CASE(A, B) \
+    if (pipe_region_dwords(A, B, Z) <= 65536u) \
+        m = std::max<uint64_t>(m, pipe_lists_bytes_t<A, B>(nd, Y, Z));
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return m;
+}
+
+hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s) {
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_pipe_lists_t<A, B>(L, lists, s);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
+}
+
+// One pipelined sweep of parity q from src to dst (as launch_sweep_i8_halo),
+// with the lists built by launch_pipe_lists for the same shape; n_cu: compute
+// units of the device (one block each at most).
+hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
+                                const uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s) {
+    const uint32_t nt = 64u * tl.ry;  // 8 or 16 waves
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_pipe_t<A, B>(L, src, dst, lists, nt, q, n_cu, s);
+    ISF_PIPE_SHAPES(ISF_CASE)
 #undef ISF_CASE
     return hipErrorInvalidValue;
 }

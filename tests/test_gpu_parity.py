@@ -457,6 +457,133 @@ def test_sweep_kernel_switches_and_reads_midway(isf):
     _assert_same(g, o)
 
 
+# ------------------------------------------------------------------ pipelined whole-sweep kernel
+# (film, shape): rows of whole 16-byte pieces (X a multiple of 32), at least one
+# region (tile + 4 dwords / 4 rows a side) wide and high; ragged tiles in x and y
+PIPE_CASES = [((320, 24, 5), (32, 16, 16)), ((352, 42, 6), (32, 16, 8)), ((576, 40, 9), (32, 16, 16)),
+              ((384, 64, 1), (32, 32, 16)), ((352, 72, 8), (32, 32, 8)), ((640, 50, 3), (64, 16, 16)),
+              ((1280, 960, 3), (32, 16, 16))]
+
+
+@pytest.mark.parametrize("film,tiling", PIPE_CASES)
+def test_pipe_kernel_matches_oracle(isf, film, tiling):
+    X, Y, Z = film
+    h = _rand_h((Y, X), Z, 7 * X + 5 * Y + Z)
+    g, o = _pair(isf, h, Z, 24680, replica=3, init=2)
+    g.set_tuning(tiling[0], tiling[1], tiling[2], (X + Y) % 2 == 0, 3)
+    assert g.get_tuning()[4] == 3
+    _say("pipe kernel", X, Y, Z, tiling)
+    steps = [(2.5, 30, 66, 0), (0.8, -45, 4, 1), (9.0, 0, 3, 1), (4.0, -7, 5, 2), (1e-3, 241, 1, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_pipe_kernel_more_tiles_than_blocks_hold(isf):
+    """A film with more tiles than the blocks of one per compute unit may take
+    (32 x 16 tiles, 9600 of them): the grid grows instead."""
+    h = _rand_h((4800, 8192), 1, 77)
+    g, o = _pair(isf, h, 1, 1234, init=2)
+    g.set_tuning(32, 16, 16, False, 3)
+    _say("pipe kernel, 8192 x 4800 x 1")
+    np.testing.assert_array_equal(g.run_sweeps(1.5, -10, 3), o.run(1.5, -10, 3).as_tuple())
+    _assert_same(g, o)
+
+
+def test_pipe_kernel_degenerate_films(isf):
+    _say("pipe kernel degenerate")
+    for h, Z in ((np.zeros((24, 320), dtype=np.uint8), 3), (np.full((24, 320), 4, dtype=np.uint8), 4),
+                 (np.ones((40, 384), dtype=np.uint8), 1)):
+        g, o = _pair(isf, h, Z, 5, init=2)
+        g.set_tuning(32, 16, 16, False, 3)
+        np.testing.assert_array_equal(g.run_sweeps(2.2, 10, 9, 3), o.run(2.2, 10, 9, 3).as_tuple())
+        _assert_same(g, o)
+
+
+def test_pipe_kernel_rejects_unsupported(isf):
+    from paper_1205_5588_amd._lib import IsfError
+
+    h = _rand_h((64, 512), 4, 1)
+    with pytest.raises(IsfError):
+        isf.Lattice(h, 4, 1, fmt=1).set_tuning(32, 16, 16, False, 3)  # bit-packed film
+    g = isf.Lattice(h, 4, 1)
+    for bad in ((32, 8, 16), (16, 16, 16), (32, 16, 4), (32, 16, 32)):
+        with pytest.raises(IsfError):
+            g.set_tuning(bad[0], bad[1], bad[2], False, 3)
+    for hh, Z in ((_rand_h((64, 328), 4, 2), 4),  # 41 dwords per row: not whole 16-byte pieces
+                  (_rand_h((64, 256), 4, 3), 4),  # narrower than one 32 x 16 region (40 dwords)
+                  (_rand_h((16, 512), 4, 4), 4),  # lower than one region (24 rows)
+                  (np.full((32, 512), 64, dtype=np.uint8), 64)):  # LDS of a 64-plane double buffer
+        with pytest.raises(IsfError):
+            isf.Lattice(hh, Z, 1).set_tuning(32, 16, 16, False, 3)
+    with pytest.raises(IsfError):
+        isf.Lattice(_rand_h((64, 512), 9, 5), 9, 1).set_tuning(32, 32, 16, False, 3)  # 32 x 32 at Z = 9
+    assert g.get_tuning()[4] == 0  # rejected shapes leave the previous tuning
+
+
+@pytest.mark.parametrize("tiling", [(32, 32, 16), (32, 16, 16)])
+def test_pipe_kernel_large_prefix(isf, tiling):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.set_tuning(tiling[0], tiling[1], tiling[2], True, 3)
+    _say("pipe kernel, large film prefix", tiling)
+    hs = c.h_nums[:1]
+    np.testing.assert_array_equal(g.ramp_field(c.T, hs, 12), cpu.hysteresis(o, c.T, hs, 12))
+    _assert_same(g, o)
+
+
+def test_pipe_kernel_equals_sweep_kernel_tscan_film(isf):
+    """Random start, high temperature on the 512 x 512 x 5 film: pipelined == single-tile whole sweep,
+    through graphs of 64 sweeps and timed launches."""
+    from isf_workloads import config_plain_tscan
+
+    c = config_plain_tscan()
+    h = c.heights()
+    a = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    b = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    a.set_tuning(16, 16, 8, True, 2)
+    b.set_tuning(32, 16, 16, True, 3)
+    _say("pipe kernel vs sweep kernel, tscan film")
+    steps = [(12.0, 0, 140, 10), (5.0, 0, 30, 0), (3.0, 15, 70, 20)]
+    np.testing.assert_array_equal(a.run_schedule(steps), b.run_schedule(steps))
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    for lat in (a, b):
+        lat.schedule_load([(2.0, -20, 6, 0)])
+    a.advance(6)
+    ms, n = b.time_launches(6)
+    assert n == 6 and ms[0] > 0.0
+    np.testing.assert_array_equal(a.records(), b.records())
+    np.testing.assert_array_equal(a.spins(), b.spins())
+
+
+def test_pipe_kernel_switches_and_reads_midway(isf):
+    """Runs of the pipelined kernel opened and closed at odd places, switching with the
+    single-tile whole sweep (other lists) and the sublattice tiles inside steps."""
+    h = _rand_h((46, 352), 6, 98)
+    steps = [(2.5, 30, 7, 2), (0.8, -45, 5, 1, 40), (6.0, 5, 9, 3)]
+    g, o = _pair(isf, h, 6, 4243, replica=5, init=2)
+    g.schedule_load(steps)
+    _say("pipe kernel switching")
+    done = 0
+    for chunk, kernel in ((3, 3), (1, 3), (4, 2), (2, 3), (5, 0), (3, 3), (1, 2), (2, 3)):
+        if kernel == 3:
+            g.set_tuning(32, 16, 16, False, 3)
+        elif kernel == 2:
+            g.set_tuning(32, 16, 8, False, 2)
+        else:
+            g.set_tuning(64, 4, 2, False, 0)
+        done += g.advance(chunk)
+        assert g.observables()["sweeps"] == done
+        if chunk == 4:
+            g.spins()
+    g.advance(100)
+    ro = np.array([o.run(*s).as_tuple() for s in steps])
+    np.testing.assert_array_equal(g.records(), ro)
+    _assert_same(g, o)
+
+
 def test_batched_whole_mode_rejects_bitpack(isf):
     from paper_1205_5588_amd._lib import IsfError
 
@@ -473,9 +600,11 @@ GATED_STEPS = [(2.5, 30, 7, 0, 40), (0.8, -45, 4, 1, 160), (9.0, 0, 5, 2, -20), 
 
 
 @pytest.mark.parametrize("kernel,tiling", [(0, (64, 4, 2)), (0, (16, 16, 1)), (1, (64, 4, 1)), (2, (32, 16, 8)),
-                                           (2, (16, 16, 4))])
-@pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1)])
+                                           (2, (16, 16, 4)), (3, (32, 16, 16))])
+@pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1), (352, 46, 6)])
 def test_gated_schedule_matches_oracle(isf, kernel, tiling, X, Y, Z):
+    if kernel == 3 and (X % 32 or X // 8 < tiling[0] + 8 or Y < tiling[1] + 8):
+        pytest.skip("film outside the pipelined kernel's shapes")
     h = _rand_h((Y, X), Z, 11 * X + Y + Z)
     g, o = _pair(isf, h, Z, 97531, replica=8, init=2)
     if kernel == 1:
@@ -492,7 +621,7 @@ def test_gated_large_film_prefix(isf):
     c = config_plain_hysteresis_large()
     h = c.heights()
     g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
-    g.set_tuning(32, 32, 16, True, 2)
+    g.set_tuning(32, 32, 16, True, 3)
     _say("gated large film prefix")
     steps = [(c.T, hn, 5, 0, 40) for hn in (120, 60, 0, -60)]
     np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
@@ -523,9 +652,10 @@ def test_gate_rejected_for_bitpacked_films(isf):
 
 
 # ------------------------------------------------------------------ PMOKE image and film statistics
-@pytest.mark.parametrize("fmt,kernel,tiling", [(0, 0, (64, 4, 2)), (0, 2, (32, 16, 8)), (1, 0, (64, 4, 1))])
+@pytest.mark.parametrize("fmt,kernel,tiling", [(0, 0, (64, 4, 2)), (0, 2, (32, 16, 8)), (1, 0, (64, 4, 1)),
+                                               (0, 3, (32, 16, 16))])
 def test_surface_image_matches_oracle(isf, fmt, kernel, tiling):
-    X = 256 if fmt else 200
+    X = 256 if fmt else (352 if kernel == 3 else 200)
     h = _rand_h((58, X), 6, 40 + fmt + kernel)
     g, o = _pair(isf, h, 6, 1357, replica=2, init=2, fmt=fmt)
     g.set_tuning(tiling[0], tiling[1], tiling[2], False, kernel)
