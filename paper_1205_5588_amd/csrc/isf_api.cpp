@@ -42,7 +42,8 @@ uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
 hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
 hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
-                                const uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s);
+                                uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s);
+hipError_t launch_pipe_reset(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
 uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t halo_lists_bytes(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t Z);
@@ -276,6 +277,8 @@ int32_t prepare_spare(isf_lattice *lat, const Tiling &tl) {
 int32_t prime_whole(isf_lattice *lat) {
     if (!lat->whole_active) {
         hipError_t e = launch_whole_prime(lat->L, lat->cur_spare ? 1u : 0u, lat->stream);
+        if (e == hipSuccess && lat->lists_ready && lat->lists_tiling.kernel == ISF_KERNEL_PIPE)
+            e = launch_pipe_reset(lat->L, lat->lists_tiling, lat->lists, lat->stream);
         if (e != hipSuccess)
             return fail(ISF_EHIP, "prime launch failed: %s", hipGetErrorString(e));
         lat->whole_active = true;

@@ -696,6 +696,12 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo_batch(const WholeEntry *__
 //   * a tile's write-back is issued after the next tile's loads are known
 //     to have landed, so waiting for one never waits for the other.
 constexpr int kPX = 4;  // halo dwords on each side along x (pipelined kernel)
+// Changed-dword lists of the pipelined kernel (per tile and sweep): entries,
+// the marker of a list that overflowed (or of a tile whose other copy must be
+// rewritten whole), and the bytes of one HBM record (count + entries).
+constexpr uint32_t kChgCap = 128;
+constexpr uint32_t kChgAll = 0xFFFFFFFFu;
+constexpr uint32_t kChgRecBytes = (4u + 2u * kChgCap + 15u) & ~15u;
 
 template <int TXD, int TYR>
 struct GeoP {
@@ -718,7 +724,13 @@ struct GeoP {
     __host__ __device__ static constexpr uint32_t cap_pieces(uint32_t Z) {
         return 1u + (cand(0, Z) + 7u) / 8u + (cand(1, Z) + 7u) / 8u + (cand(2, Z) + 7u) / 8u + (cand(3, Z) + 7u) / 8u;
     }
-    __host__ __device__ static constexpr uint32_t rec_bytes(uint32_t Z) { return (16u * cap_pieces(Z) + 255u) & ~255u; }
+    // then, per sweep parity, the tile's dwords that flipped in the last sweep
+    // of that parity (a count, kChgCap region indices; a count above kChgCap:
+    // too many to list, the whole tile is written)
+    __host__ __device__ static constexpr uint32_t chg_off(uint32_t Z) { return 16u * cap_pieces(Z); }
+    __host__ __device__ static constexpr uint32_t rec_bytes(uint32_t Z) {
+        return (chg_off(Z) + 2u * kChgRecBytes + 255u) & ~255u;
+    }
     // LDS: regions [2Z+3 planes] | lists of buffer 0 | lists of buffer 1 | row table | dword table
     __host__ __device__ static constexpr uint32_t region_words(uint32_t Z) { return (2u * Z + 3u) * PL; }
     __host__ __device__ static constexpr uint32_t list_bytes(uint32_t Z) { return 16u * cap_pieces(Z); }
@@ -808,6 +820,20 @@ __global__ __launch_bounds__(256) void k_pipe_lists(LatDev L, uint32_t nbx, uint
     }
     if (tid < 4)
         reinterpret_cast<uint32_t *>(rec)[tid] = cnt[tid];
+    // no changed-dword list yet: the first sweeps of either parity write whole tiles
+    if (tid < 2)
+        *reinterpret_cast<uint32_t *>(rec + G::chg_off(Z) + tid * kChgRecBytes) = kChgAll;
+}
+
+// Marks every tile's changed-dword lists "write the whole tile" (at the start
+// of a run: the copy a sweep writes may differ from the one it reads anywhere).
+template <int TXD, int TYR>
+__global__ __launch_bounds__(256) void k_pipe_reset_changes(uint8_t *lists, uint32_t ntiles, uint32_t Z) {
+    using G = GeoP<TXD, TYR>;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < 2u * ntiles)
+        *reinterpret_cast<uint32_t *>(lists + (size_t)(i >> 1) * G::rec_bytes(Z) + G::chg_off(Z) +
+                                      (i & 1u) * kChgRecBytes) = kChgAll;
 }
 
 // One attempt on the dword at region index qi in phase S of the pipelined
@@ -818,7 +844,7 @@ __global__ __launch_bounds__(256) void k_pipe_lists(LatDev L, uint32_t nbx, uint
 template <int S, int RX, int PL>
 __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const uint32_t *rowk, const uint32_t *dmap,
                                              const uint32_t *tab64, uint32_t gthr, uint32_t t, const LatDev &L,
-                                             int &dM, int &dE, int &acc) {
+                                             uint16_t *chg, uint32_t *chg_n, int &dM, int &dE, int &acc) {
     constexpr bool kLeft = ((S & 1) ^ (S >> 1)) == 0;  // (y + z) even: the shifted columns are j - 1
     constexpr int kB = PL + RX;                        // offset of the dword from its gather base
     constexpr int o = kLeft ? -1 : 1;
@@ -865,6 +891,10 @@ __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const ui
             dM += 2 * (cd - cu);
             dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
             acc += cu + cd;
+            // a dword belongs to one sublattice: it changes at most once per sweep
+            const uint32_t at = atomicAdd(chg_n, 1u);
+            if (at < kChgCap)
+                chg[at] = (uint16_t)qi;
         }
     }
 }
@@ -873,9 +903,10 @@ __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const ui
 template <int S, int RX, int PL, int NT>
 __device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint32_t *Rb, const uint32_t *rowk,
                                            const uint32_t *dmap, const uint32_t *tab64, uint32_t gthr, uint32_t t,
-                                           const LatDev &L, int &dM, int &dE, int &acc) {
+                                           const LatDev &L, uint16_t *chg, uint32_t *chg_n, int &dM, int &dE,
+                                           int &acc) {
     for (uint32_t i = threadIdx.x; i < n; i += NT)
-        pipe_attempt<S, RX, PL>(ls[i], Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        pipe_attempt<S, RX, PL>(ls[i], Rb, rowk, dmap, tab64, gthr, t, L, chg, chg_n, dM, dE, acc);
 }
 
 // The books of the pipelined kernel: as book_advance, with everything it reads
@@ -900,7 +931,7 @@ __device__ __forceinline__ BookNext book_next_issue(const LatDev &L, const BookL
 
 template <int TXD, int TYR, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *__restrict__ src,
-                                                      uint8_t *__restrict__ dst, const uint8_t *__restrict__ lists,
+                                                      uint8_t *__restrict__ dst, uint8_t *__restrict__ lists,
                                                       uint32_t nbx, uint32_t ntiles, uint32_t q) {
     using G = GeoP<TXD, TYR>;
     constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL, CH = G::CH;
@@ -908,6 +939,8 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     __shared__ uint32_t tab64[64];  // thresholds at n + 12 + 32 [s = +1]
     __shared__ uint32_t gthr_sh, t_sh, run_sh;
     __shared__ BookLds bk;
+    __shared__ uint16_t chg_sh[2][kChgCap];  // the tile's changed dwords, by tile parity
+    __shared__ uint32_t chg_n_sh[2];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // the wave's index, in a scalar register
@@ -994,24 +1027,46 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     int dM = 0, dE = 0, acc = 0;
     uint32_t prev = 0xFFFFFFFFu;
     char *out = reinterpret_cast<char *>(dst);
-    // Write tile `tile` (in buffer buf) back: its 16-byte pieces that hold an
-    // occupied site.  A thread keeps one piece column and row of the tile and
-    // steps through the planes.
+    // Write tile `tile` (in buffer buf, its changed dwords in list slot) to the
+    // other copy.  That copy holds the state before the previous sweep, so the
+    // dwords that changed in that sweep or in this one are all that differ; a
+    // list that overflowed (or a first sweep) writes every 16-byte piece that
+    // holds an occupied site instead.  This sweep's list is kept for the next.
     constexpr uint32_t TX4 = TXD / 4, kPiecesPerPlane = TX4 * TYR, kPlaneStep = NT / kPiecesPerPlane;
     static_assert(NT % kPiecesPerPlane == 0, "a block covers whole planes of a tile");
     const uint32_t wb_cx = 4 * (tid % TX4), wb_ry = (tid / TX4) % TYR, wb_p0 = tid / kPiecesPerPlane + 1;
-    auto write_back = [&](uint32_t tile, uint32_t buf) {
+    auto write_back = [&](uint32_t tile, uint32_t buf, uint32_t slot) {
         const uint32_t bx = tile % nbx, by = tile / nbx;
-        const uint32_t y = by * TYR + wb_ry, d = bx * TXD + wb_cx;
-        if (y >= Y || d >= nd)  // a ragged tile's part beyond the film
-            return;
-        const uint32_t *from = R + buf * (Z + 1) * PL + (wb_p0 * RYN + wb_ry + kHY) * RX + wb_cx + kPX;
-        char *to = out + (wb_p0 * planeb + y * rowb + d * 4u);
-        for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(from);
-            if (v.x != kVacant || v.y != kVacant || v.z != kVacant || v.w != kVacant)
-                *reinterpret_cast<uint4 *>(to) = v;
+        const uint32_t *Rt = R + buf * (Z + 1) * PL;
+        uint8_t *chg_rec = lists + (size_t)tile * recb + G::chg_off(Z);
+        const uint32_t *prev = reinterpret_cast<const uint32_t *>(chg_rec + (1u - q) * kChgRecBytes);
+        uint32_t *cur = reinterpret_cast<uint32_t *>(chg_rec + q * kChgRecBytes);
+        const uint32_t n_cur = chg_n_sh[slot], n_prev = prev[0];
+        if (n_cur <= kChgCap && n_prev <= kChgCap) {
+            const uint16_t *pe = reinterpret_cast<const uint16_t *>(prev + 1);
+            for (uint32_t i = tid; i < n_cur + n_prev; i += NT) {
+                const uint32_t qi = i < n_cur ? chg_sh[slot][i] : pe[i - n_cur];
+                const uint32_t p = qi / PL, rem = qi - p * PL, ry = rem / RX, cx = rem - ry * RX;
+                const uint32_t y = by * TYR + ry - kHY, d = bx * TXD + cx - kPX;  // listed dwords are the tile's
+                *reinterpret_cast<uint32_t *>(out + (p * planeb + y * rowb + d * 4u)) = Rt[qi];
+            }
+        } else {
+            const uint32_t y = by * TYR + wb_ry, d = bx * TXD + wb_cx;
+            if (y < Y && d < nd) {  // else: a ragged tile's part beyond the film
+                const uint32_t *from = Rt + (wb_p0 * RYN + wb_ry + kHY) * RX + wb_cx + kPX;
+                char *to = out + (wb_p0 * planeb + y * rowb + d * 4u);
+                for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(from);
+                    if (v.x != kVacant || v.y != kVacant || v.z != kVacant || v.w != kVacant)
+                        *reinterpret_cast<uint4 *>(to) = v;
+                }
+            }
         }
+        uint16_t *ce = reinterpret_cast<uint16_t *>(cur + 1);
+        for (uint32_t i = tid; i < min(n_cur, kChgCap); i += NT)
+            ce[i] = chg_sh[slot][i];
+        if (tid == 0)
+            cur[0] = n_cur <= kChgCap ? n_cur : kChgAll;
     };
 
     BookNext bn{};
@@ -1021,7 +1076,9 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         // this tile's loads (and the write-back of two tiles ago) have landed
         __builtin_amdgcn_s_waitcnt(0);
         if (prev != 0xFFFFFFFFu)
-            write_back(prev, buf ^ 1u);
+            write_back(prev, buf ^ 1u, buf ^ 1u);
+        if (tid == 0)
+            chg_n_sh[buf] = 0;  // list slot of this tile (its last user, two tiles ago, is written back)
         const uint32_t bx = tile % nbx, by = tile / nbx;
         const int d0 = (int)(bx * TXD), y0 = (int)(by * TYR);
         const uint32_t ynd = Y * nd;
@@ -1062,17 +1119,17 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         uint32_t *Rb = R + buf * (Z + 1) * PL;
         const uint32_t t = t_sh, gthr = gthr_sh;
         const uint32_t l1 = 8u + ((cnt.x + 7u) & ~7u), l2 = l1 + ((cnt.y + 7u) & ~7u), l3 = l2 + ((cnt.z + 7u) & ~7u);
-        pipe_phase<0, RX, PL, NT>(lb + 8, cnt.x, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        pipe_phase<0, RX, PL, NT>(lb + 8, cnt.x, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<1, RX, PL, NT>(lb + l1, cnt.y, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        pipe_phase<1, RX, PL, NT>(lb + l1, cnt.y, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<2, RX, PL, NT>(lb + l2, cnt.z, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        pipe_phase<2, RX, PL, NT>(lb + l2, cnt.z, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, Rb, rowk, dmap, tab64, gthr, t, L, dM, dE, acc);
+        pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
     }
     if (prev != 0xFFFFFFFFu)
-        write_back(prev, (k - 1u) & 1u);
+        write_back(prev, (k - 1u) & 1u, (k - 1u) & 1u);
     if (k == 0 && booker) {  // a block without tiles (not block 0: it always holds tile 0)
         book_stage(bk, br, tid);
         bn = book_next_issue(L, bk, tid);
@@ -1151,7 +1208,7 @@ void pipe_grid_of(const LatDev &L, uint32_t n_cu, uint32_t &nbx, uint32_t &tiles
 }
 
 template <int TXD, int TYR>
-hipError_t launch_pipe_t(const LatDev &L, const uint8_t *src, uint8_t *dst, const uint8_t *lists, uint32_t nt,
+hipError_t launch_pipe_t(const LatDev &L, const uint8_t *src, uint8_t *dst, uint8_t *lists, uint32_t nt,
                          uint32_t q, uint32_t n_cu, hipStream_t s) {
     uint32_t nbx, tiles, blocks;
     pipe_grid_of<TXD, TYR>(L, n_cu, nbx, tiles, blocks);
@@ -1177,6 +1234,14 @@ template <int TXD, int TYR>
 hipError_t launch_pipe_lists_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
     const uint32_t nbx = (L.nd + TXD - 1) / TXD, tiles = nbx * ((L.Y + TYR - 1) / TYR);
     hipLaunchKernelGGL((k_pipe_lists<TXD, TYR>), dim3(tiles), dim3(256), 0, s, L, nbx, lists);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+hipError_t launch_pipe_reset_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
+    const uint32_t nbx = (L.nd + TXD - 1) / TXD, tiles = nbx * ((L.Y + TYR - 1) / TYR);
+    hipLaunchKernelGGL((k_pipe_reset_changes<TXD, TYR>), dim3((2 * tiles + 255) / 256), dim3(256), 0, s, lists,
+                       tiles, L.Z);
     return hipGetLastError();
 }
 
@@ -1328,11 +1393,23 @@ hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, 
     return hipErrorInvalidValue;
 }
 
+// Start of a run of pipelined sweeps: the first sweep of either parity writes
+// whole tiles (the lists of changed dwords say nothing about the copies yet).
+hipError_t launch_pipe_reset(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s) {
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_pipe_reset_t<A, B>(L, lists, s);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
+}
+
 // One pipelined sweep of parity q from src to dst (as launch_sweep_i8_halo),
-// with the lists built by launch_pipe_lists for the same shape; n_cu: compute
-// units of the device (one block each at most).
+// with the lists built by launch_pipe_lists for the same shape (the sweep also
+// keeps its changed dwords there); n_cu: compute units of the device (one
+// block each at most).
 hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
-                                const uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s) {
+                                uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s) {
     const uint32_t nt = 64u * tl.ry;  // 8 or 16 waves
 #define ISF_CASE(A, B) \
     if (tl.tx == A && tl.ty == B) \
