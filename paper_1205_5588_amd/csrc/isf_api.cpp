@@ -40,7 +40,7 @@ uint32_t pipe_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t pipe_static_lds(uint32_t tx, uint32_t ty, uint32_t nt);
 uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
-hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
+hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, uint32_t n_cu, hipStream_t s);
 hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s);
 hipError_t launch_pipe_reset(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
@@ -263,7 +263,7 @@ int32_t prepare_spare(isf_lattice *lat, const Tiling &tl) {
     }
     const Tiling &lt = lat->lists_tiling;
     if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty || lt.kernel != tl.kernel) {
-        hipError_t e = tl.kernel == ISF_KERNEL_PIPE ? launch_pipe_lists(lat->L, tl, lat->lists, lat->stream)
+        hipError_t e = tl.kernel == ISF_KERNEL_PIPE ? launch_pipe_lists(lat->L, tl, lat->lists, lat->n_cu, lat->stream)
                                                     : launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
         if (e != hipSuccess)
             return fail(ISF_EHIP, "list launch failed: %s", hipGetErrorString(e));

@@ -21,26 +21,70 @@ namespace isf {
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).  The key and three of
 // the four counter words are uniform across a wave, so the compiler keeps the
 // key schedule and the first round's uniform product in scalar registers.
-__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
-                                       uint32_t out[4]) {
+// Rounds [R0, R1) of Philox4x32-10 on the counter c (in place); (k0, k1) is
+// the key of round 0.  Splitting the ten rounds lets a caller put other work
+// between them; the result is the same.
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    k0 += (uint32_t)R0 * 0x9E3779B9u;
+    k1 += (uint32_t)R0 * 0xBB67AE85u;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    for (int r = R0; r < R1; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
         // three-input XOR in one gfx950 instruction (truth table 0x96)
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c[1], k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c[3], k1, 0x96);
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
+}
+
+// Many calls share counter words 1 and 2 (sweep, replica) and differ in word 0
+// (the site): the parts of rounds 0 and 1 that do not involve word 0 are the
+// same for all of them and are computed once here.
+struct PhiloxShared {
+    uint32_t r0w0, r0w1;  // words 0 and 1 after round 0
+    uint32_t r1hi, r1lo;  // the round-1 product of word 0 (high and low halves)
+};
+
+__device__ __forceinline__ PhiloxShared philox_shared(uint32_t c1, uint32_t c2, uint32_t k0) {
+    PhiloxShared p;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    p.r0w0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    p.r0w1 = (uint32_t)p1;
+    const uint64_t q0 = (uint64_t)0xD2511F53u * (uint64_t)p.r0w0;
+    p.r1hi = (uint32_t)(q0 >> 32);
+    p.r1lo = (uint32_t)q0;
+    return p;
+}
+
+// Rounds 0 and 1 of the counter (c0, c1, c2, c3) from its shared part sh
+// (made by philox_shared from c1, c2 and k0); rounds 2..9 follow with
+// philox_rounds<2, 10>.
+__device__ __forceinline__ void philox_first_two(uint32_t (&c)[4], uint32_t c0, uint32_t c3, const PhiloxShared &sh,
+                                                 uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;  // round 0
+    const uint32_t w2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, w3 = (uint32_t)p0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)w2;  // round 1
+    c[0] = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), sh.r0w1, k0 + 0x9E3779B9u, 0x96);
+    c[1] = (uint32_t)p1;
+    c[2] = __builtin_amdgcn_bitop3_b32(sh.r1hi, w3, k1 + 0xBB67AE85u, 0x96);
+    c[3] = sh.r1lo;
+}
+
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                       uint32_t out[4]) {
+    uint32_t c[4] = {c0, c1, c2, c3};
+    philox_rounds<0, 10>(c, k0, k1);
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
 }
 
 // Switching-field gate of Eq. (9) (steps 4-5 of the algorithm in Section 5):

@@ -695,7 +695,8 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_halo_batch(const WholeEntry *__
 //     occupied dwords' entries;
 //   * a tile's write-back is issued after the next tile's loads are known
 //     to have landed, so waiting for one never waits for the other.
-constexpr int kPX = 4;  // halo dwords on each side along x (pipelined kernel)
+constexpr int kPX = 4;               // halo dwords on each side along x (pipelined kernel)
+constexpr uint32_t kPipeTiles = 32;  // most tiles per block of the pipelined kernel
 // Changed-dword lists of the pipelined kernel (per tile and sweep): entries,
 // the marker of a list that overflowed (or of a tile whose other copy must be
 // rewritten whole), and the bytes of one HBM record (count + entries).
@@ -836,48 +837,113 @@ __global__ __launch_bounds__(256) void k_pipe_reset_changes(uint8_t *lists, uint
                                       (i & 1u) * kChgRecBytes) = kChgAll;
 }
 
+// The tiles each block of a pipelined sweep takes: order[b * kmax + k] is block
+// b's k-th tile (kNoTile past its last one).  Blocks b with b % nb == x (nb =
+// min(8, G) bands, one per XCD where blocks are dealt to the 8 XCDs round
+// robin) share band x of the tiles, [x * per, (x + 1) * per): neighbouring
+// tiles, whose halos overlap, then run on one XCD and share its L2.  Tiles
+// differ up to tenfold in occupied dwords (the height map's hills and valleys)
+// and a sweep lasts as long as its busiest block, so within a band the tiles
+// are sorted by their listed dwords, heaviest first, and dealt back and forth:
+// round r goes to the band's blocks in order when r is even and in reverse when
+// r is odd (a last, incomplete round in order), pairing the heaviest tiles
+// with the lightest.  One block; a counting sort on listed dwords / 64 (ties in
+// any order: which block sweeps a tile does not change the result).
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+template <int TXD, int TYR>
+__global__ __launch_bounds__(1024) void k_pipe_order(uint8_t *lists, uint32_t ntiles, uint32_t Z, uint32_t G,
+                                                     uint32_t kmax) {
+    using Geom = GeoP<TXD, TYR>;
+    __shared__ uint32_t start[8][256];
+    const uint32_t tid = threadIdx.x, recb = Geom::rec_bytes(Z);
+    const uint32_t nb = min(8u, G), per = (ntiles + nb - 1) / nb;
+    uint32_t *order = reinterpret_cast<uint32_t *>(lists + (size_t)ntiles * recb);
+    auto key_of = [&](uint32_t tile) -> uint32_t {
+        const uint4 c = *reinterpret_cast<const uint4 *>(lists + (size_t)tile * recb);
+        return 255u - min((c.x + c.y + c.z + c.w) / 64u, 255u);  // heaviest first
+    };
+    for (uint32_t i = tid; i < 8 * 256; i += 1024)
+        start[i >> 8][i & 255u] = 0;
+    for (uint32_t i = tid; i < G * kmax; i += 1024)
+        order[i] = kNoTile;
+    __syncthreads();
+    for (uint32_t t = tid; t < ntiles; t += 1024)
+        atomicAdd(&start[t / per][key_of(t)], 1u);
+    __syncthreads();
+    if (tid < nb) {  // exclusive prefix sums, one band per thread
+        uint32_t acc = 0;
+        for (int k = 0; k < 256; ++k) {
+            const uint32_t c = start[tid][k];
+            start[tid][k] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < ntiles; t += 1024) {
+        const uint32_t x = t / per;
+        const uint32_t p = atomicAdd(&start[x][key_of(t)], 1u);  // rank within the band, heaviest first
+        const uint32_t gbx = (G - x + nb - 1) / nb;              // the band's blocks: x, x + nb, ...
+        const uint32_t nx = min(ntiles, (x + 1) * per) - x * per;
+        const uint32_t r = p / gbx, j = p - r * gbx;
+        const uint32_t jj = (p < nx / gbx * gbx && (r & 1u)) ? gbx - 1u - j : j;
+        order[(jj * nb + x) * kmax + r] = t;
+    }
+}
+
 // One attempt on the dword at region index qi in phase S of the pipelined
 // kernel.  tab64 holds the thresholds at n + 12 + 32 [s = +1], so the key of
 // four sites is one shift and OR of their neighbour sums.  (Two dwords per
-// iteration, interleaved, measured slower here: the register pressure costs
-// more than the overlap gains.)
+// thread and iteration, interleaved, measured slower here: the register
+// pressure costs more than the overlap gains.)
 template <int S, int RX, int PL>
 __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const uint32_t *rowk, const uint32_t *dmap,
-                                             const uint32_t *tab64, uint32_t gthr, uint32_t t, const LatDev &L,
-                                             uint16_t *chg, uint32_t *chg_n, int &dM, int &dE, int &acc) {
+                                             const uint32_t *tab64, uint32_t gthr, uint32_t t, const PhiloxShared &psh,
+                                             const LatDev &L, uint16_t *chg, uint32_t *chg_n, int &dM, int &dE,
+                                             int &acc) {
     constexpr bool kLeft = ((S & 1) ^ (S >> 1)) == 0;  // (y + z) even: the shifted columns are j - 1
-    constexpr int kB = PL + RX;                        // offset of the dword from its gather base
     constexpr int o = kLeft ? -1 : 1;
     auto sh = [](uint32_t cur, uint32_t other) {
         return kLeft ? __builtin_amdgcn_alignbyte(cur, other, 3) : __builtin_amdgcn_alignbyte(other, cur, 1);
     };
     const uint32_t row = qi / RX, cx = qi - row * RX;
     const uint32_t rk = rowk[row], dm = dmap[cx];
-    // gather base at the lowest neighbour: every offset below is a non-negative
-    // immediate (the empty asm keeps the compiler from folding it back; the
-    // pointer is an LDS one so that the reads stay LDS reads)
-    const lds_u32_t *Rg = (const lds_u32_t *)(Rb + (qi - kB));
-    asm volatile("" : "+v"(Rg));
-    const uint32_t a = Rg[kB];
-    const uint32_t a1 = Rg[kB - RX], a2 = Rg[kB + RX];
-    const uint32_t b1 = Rg[kB - PL], b2 = Rg[kB + PL];
-    const uint32_t a1o = Rg[kB - RX + o], a2o = Rg[kB + RX + o];
-    const uint32_t b1o = Rg[kB - PL + o], b2o = Rg[kB + PL + o];
-    const uint32_t e1 = Rg[0], e2 = Rg[kB - PL + RX];
-    const uint32_t e3 = Rg[kB + PL - RX], e4 = Rg[kB + PL + RX];
+    // the draw needs only the row and dword tables: its counter is formed before
+    // the neighbour reads are issued (the empty asm orders them), so the draw
+    // runs while those reads are in flight
+    const uint32_t site4 = (rk & 0x7FFFFFFFu) + (dm & 0x7FFFFFFFu);
+    asm volatile("" ::"v"(site4) : "memory");
+    // The 13 reads from three bases, one per plane (z - 1, z, z + 1), each at
+    // the row below and one dword further down: within a plane the reads lie at
+    // most 2 RX + 2 dwords apart, so pairs of them become single two-address
+    // reads with immediate offsets (the empty asm keeps the compiler from
+    // folding the bases back; the pointers are LDS ones so that the reads stay
+    // LDS reads).
+    const lds_u32_t *Pm = (const lds_u32_t *)(Rb + (qi - PL - RX - 1));  // plane z - 1, row y - 1
+    const lds_u32_t *P0 = Pm + PL, *Pp = Pm + 2 * PL;
+    asm volatile("" : "+v"(Pm), "+v"(P0), "+v"(Pp));
+    const uint32_t e1 = Pm[1], b1 = Pm[RX + 1], b1o = Pm[RX + 1 + o], e2 = Pm[2 * RX + 1];
+    const uint32_t a1 = P0[1], a1o = P0[1 + o], a = P0[RX + 1], a2 = P0[2 * RX + 1], a2o = P0[2 * RX + 1 + o];
+    const uint32_t e3 = Pp[1], b2 = Pp[RX + 1], b2o = Pp[RX + 1 + o], e4 = Pp[2 * RX + 1];
+    // six rounds of the draw while the neighbour reads are in flight, the last
+    // four while the threshold reads are (the empty asm pins the split)
+    uint32_t u[4];
+    philox_first_two(u, site4, (uint32_t)S, psh, L.key0, L.key1);
+    philox_rounds<2, 6>(u, L.key0, L.key1);
+    asm volatile("" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]));
     const uint32_t sum = (a1 + a2) + (b1 + b2) + ((sh(a1, a1o) + sh(a2, a2o)) + (sh(b1, b1o) + sh(b2, b2o))) +
                          ((e1 + e2) + (e3 + e4));
-    const uint32_t site4 = (rk & 0x7FFFFFFFu) + (dm & 0x7FFFFFFFu);
-    uint32_t u[4];
-    philox(site4, t, L.replica, (uint32_t)S, L.key0, L.key1, u);
     const uint32_t key = sum | (((a >> 1) & 0x01010101u) << 5);  // n + 12 + 32 [s = +1] <= 56
+    uint32_t thr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        thr[j] = tab64[(key >> (8 * j)) & 0xFFu];
+    asm volatile("" ::: "memory");
+    philox_rounds<6, 10>(u, L.key0, L.key1);
     uint32_t f = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        // exact single test: see the acceptance note of the single-tile kernel
-        const uint32_t thr = tab64[(key >> (8 * j)) & 0xFFu];
-        f |= (min(u[j], 0xFFFFFFFEu) < thr) ? (2u << (8 * j)) : 0u;
-    }
+    for (int j = 0; j < 4; ++j)  // exact single test: see the acceptance note of the single-tile kernel
+        f |= (min(u[j], 0xFFFFFFFEu) < thr[j]) ? (2u << (8 * j)) : 0u;
     f &= (~a & 0x01010101u) << 1;  // vacancies never flip
     if (f)
         f &= gate_mask(gthr, site4, t, L.replica, (uint32_t)S, L.key0, L.key1);
@@ -899,14 +965,22 @@ __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const ui
     }
 }
 
-// All dwords of phase S listed in ls[0 .. n), one per thread and iteration.
+// All dwords of phase S listed in ls[0 .. n), one per thread and iteration;
+// q0: the thread's first entry, read when the tile started.  The next entry is
+// read before the current attempt, so the few waves that take a second entry
+// at the end of the phase do not wait for it.
 template <int S, int RX, int PL, int NT>
-__device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint32_t *Rb, const uint32_t *rowk,
-                                           const uint32_t *dmap, const uint32_t *tab64, uint32_t gthr, uint32_t t,
-                                           const LatDev &L, uint16_t *chg, uint32_t *chg_n, int &dM, int &dE,
-                                           int &acc) {
-    for (uint32_t i = threadIdx.x; i < n; i += NT)
-        pipe_attempt<S, RX, PL>(ls[i], Rb, rowk, dmap, tab64, gthr, t, L, chg, chg_n, dM, dE, acc);
+__device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint32_t q0, uint32_t *Rb,
+                                           const uint32_t *rowk, const uint32_t *dmap, const uint32_t *tab64,
+                                           uint32_t gthr, uint32_t t, const PhiloxShared &psh, const LatDev &L,
+                                           uint16_t *chg, uint32_t *chg_n, int &dM, int &dE, int &acc) {
+    uint32_t i = threadIdx.x, q = q0;
+    while (i < n) {
+        const uint32_t nxt = i + NT < n ? (uint32_t)ls[i + NT] : 0u;
+        pipe_attempt<S, RX, PL>(q, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg, chg_n, dM, dE, acc);
+        q = nxt;
+        i += NT;
+    }
 }
 
 // The books of the pipelined kernel: as book_advance, with everything it reads
@@ -932,7 +1006,7 @@ __device__ __forceinline__ BookNext book_next_issue(const LatDev &L, const BookL
 template <int TXD, int TYR, int NT>
 __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *__restrict__ src,
                                                       uint8_t *__restrict__ dst, uint8_t *__restrict__ lists,
-                                                      uint32_t nbx, uint32_t ntiles, uint32_t q) {
+                                                      uint32_t nbx, uint32_t ntiles, uint32_t kmax, uint32_t q) {
     using G = GeoP<TXD, TYR>;
     constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL, CH = G::CH;
     extern __shared__ __align__(16) uint8_t smb[];
@@ -941,6 +1015,7 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     __shared__ BookLds bk;
     __shared__ uint16_t chg_sh[2][kChgCap];  // the tile's changed dwords, by tile parity
     __shared__ uint32_t chg_n_sh[2];
+    __shared__ uint32_t my_tiles[kPipeTiles];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // the wave's index, in a scalar register
@@ -954,14 +1029,12 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     const uint32_t planeb = Y * rowb;  // the host checks that (Z + 2) planes fit 32-bit offsets
     const uint32_t recb = G::rec_bytes(Z);
 
-    // This block's tiles: block b sits on XCD b % 8, which works through the
-    // band of tiles [x * per_xcd, (x + 1) * per_xcd); its blocks take every
-    // (grid / 8)-th tile of the band, so at any moment an XCD works on a
-    // contiguous run of tiles whose halos overlap in its L2.
-    const uint32_t xcd = blockIdx.x & 7u, gb = gridDim.x >> 3;
-    const uint32_t per_xcd = (ntiles + 7u) / 8u;
-    const uint32_t t_first = xcd * per_xcd + (blockIdx.x >> 3);
-    const uint32_t t_end = min((xcd + 1u) * per_xcd, ntiles);
+    // This block's tiles, in the order k_pipe_order made (order[b kmax + k],
+    // kNoTile past the last).  The first index is a uniform load issued before
+    // anything is stored (a scalar load, which no vector load waits behind) and
+    // starts the first tile's loads; the others go to LDS for the tile loop.
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(lists + (size_t)ntiles * recb) + blockIdx.x * kmax;
+    const uint32_t t0 = order[0];
 
     // Issue the loads of a tile's planes 1..Z and of its whole list record
     // (at capacity: its length would be one more memory round trip) into
@@ -1004,9 +1077,11 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     constexpr uint32_t PL4 = PL / 4;
     for (uint32_t i = tid; i < 3u * PL4; i += NT)
         reinterpret_cast<uint4 *>(R + (i / PL4) * (Z + 1) * PL)[i % PL4] = make_uint4(kVacant, kVacant, kVacant, kVacant);
-    if (t_first < t_end)
-        issue(t_first, 0);
-    const bool booker = blockIdx.x == 0 && tid < 64;  // block 0 holds tile 0 and keeps the books
+    // Everything else the block reads before its first tile (thresholds, sweep
+    // position, its other tiles' indices, the books) is loaded into registers
+    // before the first tile's loads are issued and stored to LDS after they
+    // have landed: stored at once, each would wait behind them.
+    const bool booker = blockIdx.x == 0 && tid < 64;  // block 0 keeps the books
     BookRegs br;
     uint32_t cur_tab = 0;
     if (booker) {
@@ -1014,15 +1089,19 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         cur_tab = tid < kTableWords ? L.pos[q].table[tid] : 0u;
     }
     const SweepPos &P = L.pos[q];
+    uint32_t pro_tab = 0, pro_tile = 0, pro_gthr = 0, pro_t = 0, pro_run = 0;
     if (tid < 64) {
         const uint32_t up = tid >> 5, m = tid & 31u;
-        tab64[tid] = m < 25u ? P.table[25u * up + m] : 0u;
+        pro_tab = m < 25u ? P.table[25u * up + m] : 0u;
+        pro_tile = tid < kmax ? order[tid] : kNoTile;  // kmax <= kPipeTiles
     }
     if (tid == 0) {
-        gthr_sh = P.table[kGateWord];
-        t_sh = (uint32_t)P.t;
-        run_sh = P.run;
+        pro_gthr = P.table[kGateWord];
+        pro_t = (uint32_t)P.t;
+        pro_run = P.run;
     }
+    if (t0 != kNoTile)
+        issue(t0, 0);
 
     int dM = 0, dE = 0, acc = 0;
     uint32_t prev = 0xFFFFFFFFu;
@@ -1043,13 +1122,16 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         uint32_t *cur = reinterpret_cast<uint32_t *>(chg_rec + q * kChgRecBytes);
         const uint32_t n_cur = chg_n_sh[slot], n_prev = prev[0];
         if (n_cur <= kChgCap && n_prev <= kChgCap) {
-            const uint16_t *pe = reinterpret_cast<const uint16_t *>(prev + 1);
-            for (uint32_t i = tid; i < n_cur + n_prev; i += NT) {
-                const uint32_t qi = i < n_cur ? chg_sh[slot][i] : pe[i - n_cur];
+            auto put = [&](uint32_t qi) {  // listed dwords are the tile's own
                 const uint32_t p = qi / PL, rem = qi - p * PL, ry = rem / RX, cx = rem - ry * RX;
-                const uint32_t y = by * TYR + ry - kHY, d = bx * TXD + cx - kPX;  // listed dwords are the tile's
+                const uint32_t y = by * TYR + ry - kHY, d = bx * TXD + cx - kPX;
                 *reinterpret_cast<uint32_t *>(out + (p * planeb + y * rowb + d * 4u)) = Rt[qi];
-            }
+            };
+            const uint16_t *pe = reinterpret_cast<const uint16_t *>(prev + 1);
+            for (uint32_t i = tid; i < n_cur; i += NT)
+                put(chg_sh[slot][i]);
+            for (uint32_t i = tid; i < n_prev; i += NT)
+                put(pe[i]);
         } else {
             const uint32_t y = by * TYR + wb_ry, d = bx * TXD + wb_cx;
             if (y < Y && d < nd) {  // else: a ragged tile's part beyond the film
@@ -1071,7 +1153,10 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
 
     BookNext bn{};
     uint32_t k = 0;
-    for (uint32_t tile = t_first; tile < t_end; tile += gb, ++k) {
+    for (; k < kmax; ++k) {
+        const uint32_t tile = k ? my_tiles[k] : t0;  // my_tiles is read after the first tile's barriers
+        if (tile == kNoTile)  // uniform
+            break;
         const uint32_t buf = k & 1u;
         // this tile's loads (and the write-back of two tiles ago) have landed
         __builtin_amdgcn_s_waitcnt(0);
@@ -1099,9 +1184,21 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
                 dmap[c] = (uint32_t)d | (own ? 0x80000000u : 0u);
             }
         }
-        if (booker && k == 0) {
-            book_stage(bk, br, tid);
-            bn = book_next_issue(L, bk, tid);  // lands while the tiles are swept
+        if (k == 0) {
+            if (tid < 64) {
+                tab64[tid] = pro_tab;
+                if (tid < kPipeTiles)
+                    my_tiles[tid] = pro_tile;
+            }
+            if (tid == 0) {
+                gthr_sh = pro_gthr;
+                t_sh = pro_t;
+                run_sh = pro_run;
+            }
+            if (booker) {
+                book_stage(bk, br, tid);
+                bn = book_next_issue(L, bk, tid);  // lands while the tiles are swept
+            }
         }
         __syncthreads();
         const uint16_t *lb = reinterpret_cast<const uint16_t *>(LB + buf * G::list_bytes(Z));
@@ -1109,8 +1206,9 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         // of LDS behind those loads would wait for them
         const uint4 cnt = *reinterpret_cast<const uint4 *>(lb);
         // the next tile streams into the other buffer while this one is swept
-        if (tile + gb < t_end)
-            issue(tile + gb, buf ^ 1u);
+        const uint32_t nxt = k + 1 < kmax ? my_tiles[k + 1] : kNoTile;
+        if (nxt != kNoTile)
+            issue(nxt, buf ^ 1u);
         prev = tile;
         if (!run_sh) {  // uniform: the schedule is finished; nothing flips
             lds_barrier();
@@ -1118,19 +1216,24 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         }
         uint32_t *Rb = R + buf * (Z + 1) * PL;
         const uint32_t t = t_sh, gthr = gthr_sh;
+        const PhiloxShared psh = philox_shared(t, L.replica, L.key0);  // the sweep's common draw parts
         const uint32_t l1 = 8u + ((cnt.x + 7u) & ~7u), l2 = l1 + ((cnt.y + 7u) & ~7u), l3 = l2 + ((cnt.z + 7u) & ~7u);
-        pipe_phase<0, RX, PL, NT>(lb + 8, cnt.x, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
+        // each thread's first entry of every phase, read together (the lists do
+        // not change during the phases)
+        const uint32_t f0 = tid < cnt.x ? lb[8 + tid] : 0u, f1 = tid < cnt.y ? lb[l1 + tid] : 0u;
+        const uint32_t f2 = tid < cnt.z ? lb[l2 + tid] : 0u, f3 = tid < cnt.w ? lb[l3 + tid] : 0u;
+        pipe_phase<0, RX, PL, NT>(lb + 8, cnt.x, f0, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<1, RX, PL, NT>(lb + l1, cnt.y, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
+        pipe_phase<1, RX, PL, NT>(lb + l1, cnt.y, f1, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<2, RX, PL, NT>(lb + l2, cnt.z, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
+        pipe_phase<2, RX, PL, NT>(lb + l2, cnt.z, f2, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
-        pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, Rb, rowk, dmap, tab64, gthr, t, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
+        pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, f3, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
     }
     if (prev != 0xFFFFFFFFu)
         write_back(prev, (k - 1u) & 1u, (k - 1u) & 1u);
-    if (k == 0 && booker) {  // a block without tiles (not block 0: it always holds tile 0)
+    if (k == 0 && booker) {  // a block without tiles (never block 0)
         book_stage(bk, br, tid);
         bn = book_next_issue(L, bk, tid);
     }
@@ -1199,26 +1302,36 @@ uint64_t lists_bytes_t(uint32_t nd, uint32_t Y, uint32_t Z) {
     return tiles * Geo<TXD, TYR>::rec_bytes(Z);
 }
 
+// Blocks of a pipelined sweep (one per compute unit, or more where a block
+// would get more than kPipeTiles tiles) and kmax, the most tiles a block gets:
+// the nb = min(8, blocks) bands hold ceil(tiles / nb) tiles each and at least
+// floor(blocks / nb) blocks.
 template <int TXD, int TYR>
-void pipe_grid_of(const LatDev &L, uint32_t n_cu, uint32_t &nbx, uint32_t &tiles, uint32_t &blocks) {
+void pipe_grid_of(const LatDev &L, uint32_t n_cu, uint32_t &nbx, uint32_t &tiles, uint32_t &blocks, uint32_t &kmax) {
     nbx = (L.nd + TXD - 1) / TXD;
     tiles = nbx * ((L.Y + TYR - 1) / TYR);
-    const uint32_t per_xcd = (tiles + 7) / 8;
-    blocks = 8u * std::max(1u, std::min((n_cu + 7) / 8, per_xcd));  // one block per compute unit at most
+    blocks = std::max(1u, std::min(n_cu, tiles));
+    for (;;) {
+        const uint32_t nb = std::min(8u, blocks), per = (tiles + nb - 1) / nb;
+        kmax = (per + blocks / nb - 1) / (blocks / nb);
+        if (kmax <= kPipeTiles)
+            break;
+        blocks += nb;
+    }
 }
 
 template <int TXD, int TYR>
 hipError_t launch_pipe_t(const LatDev &L, const uint8_t *src, uint8_t *dst, uint8_t *lists, uint32_t nt,
                          uint32_t q, uint32_t n_cu, hipStream_t s) {
-    uint32_t nbx, tiles, blocks;
-    pipe_grid_of<TXD, TYR>(L, n_cu, nbx, tiles, blocks);
+    uint32_t nbx, tiles, blocks, kmax;
+    pipe_grid_of<TXD, TYR>(L, n_cu, nbx, tiles, blocks, kmax);
     const size_t lds = GeoP<TXD, TYR>::lds_bytes(L.Z);
     if (nt == 1024)
         hipLaunchKernelGGL((k_sweep_i8_pipe<TXD, TYR, 1024>), dim3(blocks), dim3(1024), lds, s, L, src, dst, lists,
-                           nbx, tiles, q);
+                           nbx, tiles, kmax, q);
     else
         hipLaunchKernelGGL((k_sweep_i8_pipe<TXD, TYR, 512>), dim3(blocks), dim3(512), lds, s, L, src, dst, lists,
-                           nbx, tiles, q);
+                           nbx, tiles, kmax, q);
     return hipGetLastError();
 }
 
@@ -1231,9 +1344,11 @@ uint32_t pipe_static_lds_t(uint32_t nt) {
 }
 
 template <int TXD, int TYR>
-hipError_t launch_pipe_lists_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
-    const uint32_t nbx = (L.nd + TXD - 1) / TXD, tiles = nbx * ((L.Y + TYR - 1) / TYR);
+hipError_t launch_pipe_lists_t(const LatDev &L, uint8_t *lists, uint32_t n_cu, hipStream_t s) {
+    uint32_t nbx, tiles, blocks, kmax;
+    pipe_grid_of<TXD, TYR>(L, n_cu, nbx, tiles, blocks, kmax);
     hipLaunchKernelGGL((k_pipe_lists<TXD, TYR>), dim3(tiles), dim3(256), 0, s, L, nbx, lists);
+    hipLaunchKernelGGL((k_pipe_order<TXD, TYR>), dim3(1), dim3(1024), 0, s, lists, tiles, L.Z, blocks, kmax);
     return hipGetLastError();
 }
 
@@ -1248,7 +1363,8 @@ hipError_t launch_pipe_reset_t(const LatDev &L, uint8_t *lists, hipStream_t s) {
 template <int TXD, int TYR>
 uint64_t pipe_lists_bytes_t(uint32_t nd, uint32_t Y, uint32_t Z) {
     const uint64_t tiles = (uint64_t)((nd + TXD - 1) / TXD) * ((Y + TYR - 1) / TYR);
-    return tiles * GeoP<TXD, TYR>::rec_bytes(Z);
+    // records, then the tile order: blocks x kmax entries, blocks <= tiles and kmax <= kPipeTiles
+    return tiles * GeoP<TXD, TYR>::rec_bytes(Z) + (4ull * kPipeTiles * tiles + 255) / 256 * 256;
 }
 
 }  // namespace
@@ -1384,10 +1500,10 @@ uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z) {
     return m;
 }
 
-hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s) {
+hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, uint32_t n_cu, hipStream_t s) {
 #define ISF_CASE(A, B) \
     if (tl.tx == A && tl.ty == B) \
-        return launch_pipe_lists_t<A, B>(L, lists, s);
+        return launch_pipe_lists_t<A, B>(L, lists, n_cu, s);
     ISF_PIPE_SHAPES(ISF_CASE)
 #undef ISF_CASE
     return hipErrorInvalidValue;
