@@ -49,6 +49,9 @@ def lib():
         L.orc_run_gated.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
         L.orc_run_gated.restype = ctypes.c_int
+        L.orc_run_full.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.orc_run_full.restype = ctypes.c_int
         L.orc_gate_threshold.argtypes = [ctypes.c_int32, ctypes.c_double]
         L.orc_gate_threshold.restype = ctypes.c_uint32
         L.orc_surface_image.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -117,11 +120,13 @@ class Film:
     def set_order(self, order: int) -> None:
         lib().orc_set_order(self._p, int(order))
 
-    def run(self, T: float, h_num: int, n_sweeps: int, n_discard: int = 0, hs_num: int = 0) -> Record:
-        """n_sweeps sweeps at (T, H = h_num/20), behind the switching-field gate of h_s = hs_num/20."""
+    def run(self, T: float, h_num: int, n_sweeps: int, n_discard: int = 0, hs_num: int = 0,
+            an_num: int = 0) -> Record:
+        """n_sweeps sweeps at (T, H = h_num/20), behind the switching-field gate of h_s = hs_num/20,
+        with the anisotropy field h_an = an_num/20 of Eq. (7) (M frozen per sublattice phase)."""
         r = Record()
-        rc = lib().orc_run_gated(self._p, float(T), int(h_num), int(hs_num), int(n_sweeps), int(n_discard),
-                                 ctypes.byref(r))
+        rc = lib().orc_run_full(self._p, float(T), int(h_num), int(hs_num), int(an_num), int(n_sweeps),
+                                int(n_discard), ctypes.byref(r))
         if rc != 0:
             raise ValueError("oracle: invalid run arguments")
         return r

@@ -40,7 +40,16 @@
  *     does not matter: the flip happens iff both pass, for downhill moves too;
  *   - one sweep visits the four sublattices sigma = (y mod 2) + 2 (z mod 2)
  *     in the order 0, 1, 2, 3; every occupied site of the sublattice gets one
- *     attempt.
+ *     attempt;
+ *   - anisotropy field of Eq. (7) (Section 5): the Hamiltonian gains the
+ *     term -h_an |M|, h_an = an_num / 20 >= 0, which favours the sign of the
+ *     spin excess.  The term couples every site to the global M, and the
+ *     sites of one sublattice are updated together, so M is frozen at its
+ *     value at the start of each sublattice phase: a flip of spin s then
+ *     changes q by the anisotropy energy difference
+ *     10 (E_an(M - 2s) - E_an(M)) = -an_num (|M - 2s| - |M|) / 2 with that
+ *     M.  With one site per sublattice this is exactly serial Metropolis on
+ *     the Hamiltonian of Eq. (7).
  *
  * Build: gcc -O2 -std=c11 -fPIC -shared [-fopenmp] isf_oracle.c -lm
  * (no -ffast-math: the acceptance thresholds come from libm exp in IEEE
@@ -267,17 +276,30 @@ void orc_init(orc_film *f, int mode)
 
 void orc_set_order(orc_film *f, int order) { f->order = order; }
 
+/* Anisotropy part of q (tenths of the energy) for flipping spin s while the
+ * magnetisation is M: 10 (E_an(M - 2s) - E_an(M)) with E_an(M) = -h_an |M|
+ * and h_an = an_num / 20 (Eq. 7).  |M - 2s| - |M| is -2, 0 or 2, so the
+ * result is an integer. */
+static int32_t anisotropy_q(int64_t M, int s, int32_t an_num)
+{
+    int64_t before = M < 0 ? -M : M;
+    int64_t after = (M - 2 * s) < 0 ? -(M - 2 * s) : (M - 2 * s);
+    return (int32_t)(-(int64_t)an_num * (after - before) / 2);
+}
+
 /* One Metropolis attempt at an occupied site (steps 1-3 of Section 5),
- * behind the switching-field gate (steps 4-5) when gate != sentinel. */
-static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const uint32_t thr[2][25], uint32_t gate,
-                    int64_t *dM, int64_t *dE, int64_t *acc)
+ * behind the switching-field gate (steps 4-5) when gate != sentinel.
+ * aq[s > 0] is the anisotropy part of q for the site's spin s, and thr the
+ * thresholds of the full q = s (20 n + h_num) + aq[s > 0]. */
+static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const int32_t aq[2],
+                    const uint32_t thr[2][25], uint32_t gate, int64_t *dM, int64_t *dE, int64_t *acc)
 {
     size_t c = cell(f, x, y, z);
     if (gate != 0xFFFFFFFFu && !(draw(f, x, y, z, (uint32_t)f->t, 2u) < gate))
         return;                              /* the gate keeps the spin's orientation */
     int s = f->s[c];
     int n = neighbour_sum(f, x, y, z);
-    int32_t q = s * (20 * n + h_num);      /* 10 * (E2 - E1) */
+    int32_t q = s * (20 * n + h_num) + aq[s > 0];  /* 10 * (E2 - E1) */
     int accept;
     if (q <= 0) {
         accept = 1;                          /* E2 <= E1 */
@@ -293,14 +315,31 @@ static void attempt(orc_film *f, int x, int y, int z, int32_t h_num, const uint3
     }
 }
 
-/* One sweep at (T, h_num): sublattices 0..3 in turn.  Returns accepted flips. */
-static int64_t sweep(orc_film *f, int32_t h_num, const uint32_t thr[2][25], uint32_t gate)
+/* One sweep at (T, h_num): sublattices 0..3 in turn.  Returns accepted flips.
+ * thr0 is the table without anisotropy; with an_num != 0 each phase builds
+ * its own from the magnetisation at the phase's start. */
+static int64_t sweep(orc_film *f, double T, int32_t h_num, int32_t an_num, const uint32_t thr0[2][25],
+                     uint32_t gate)
 {
     int64_t acc_total = 0;
     for (int sigma = 0; sigma < 4; ++sigma) {
         int py = sigma & 1, pz = sigma >> 1;
         int nrows = f->Z * f->Y;
         int64_t dM = 0, dE = 0, acc = 0;
+        int32_t aq[2] = {0, 0};
+        uint32_t thr_an[2][25];
+        const uint32_t(*thr)[25] = thr0;
+        if (an_num != 0) {
+            /* M frozen for the phase */
+            aq[0] = anisotropy_q(f->M, -1, an_num);
+            aq[1] = anisotropy_q(f->M, 1, an_num);
+            for (int si = 0; si < 2; ++si) {
+                int s = si ? 1 : -1;
+                for (int n = -12; n <= 12; ++n)
+                    thr_an[si][n + 12] = orc_threshold(s * (20 * n + h_num) + aq[si], T);
+            }
+            thr = (const uint32_t(*)[25])thr_an;
+        }
         /* Sites of one sublattice share no bond, so every order of visiting
          * them gives the same result; rows run in parallel when OpenMP is on. */
 #pragma omp parallel for schedule(static) reduction(+ : dM, dE, acc) if ((int64_t)nrows * f->X >= 65536)
@@ -316,7 +355,7 @@ static int64_t sweep(orc_film *f, int32_t h_num, const uint32_t thr[2][25], uint
             for (int xi = 0; xi < f->X; ++xi) {
                 int x = f->order == 1 ? f->X - 1 - xi : xi;
                 if (f->occ[cell(f, x, y, z)])
-                    attempt(f, x, y, z, h_num, thr, gate, &dM, &dE, &acc);
+                    attempt(f, x, y, z, h_num, aq, thr, gate, &dM, &dE, &acc);
             }
         }
         f->M += dM;
@@ -338,11 +377,12 @@ typedef struct {
     int64_t accepted;
 } orc_record;
 
-/* n_sweeps sweeps at (T, h_num) behind the switching-field gate of hs_num. */
-int orc_run_gated(orc_film *f, double T, int32_t h_num, int32_t hs_num, uint32_t n_sweeps, uint32_t n_discard,
-                  orc_record *rec)
+/* n_sweeps sweeps at (T, h_num) behind the switching-field gate of hs_num,
+ * with the anisotropy field h_an = an_num / 20 >= 0 of Eq. (7). */
+int orc_run_full(orc_film *f, double T, int32_t h_num, int32_t hs_num, int32_t an_num, uint32_t n_sweeps,
+                 uint32_t n_discard, orc_record *rec)
 {
-    if (!(T > 0.0) || n_discard > n_sweeps)
+    if (!(T > 0.0) || n_discard > n_sweeps || an_num < 0)
         return -1;
     if (f->order == 2 && (f->Z * f->Y) % 7919 == 0)
         return -1;
@@ -352,7 +392,7 @@ int orc_run_gated(orc_film *f, double T, int32_t h_num, int32_t hs_num, uint32_t
     orc_record r;
     memset(&r, 0, sizeof r);
     for (uint32_t i = 0; i < n_sweeps; ++i) {
-        int64_t acc = sweep(f, h_num, thr, gate);
+        int64_t acc = sweep(f, T, h_num, an_num, (const uint32_t(*)[25])thr, gate);
         if (i >= n_discard) {
             r.sum_M += f->M;
             r.sum_absM += f->M < 0 ? -f->M : f->M;
@@ -365,6 +405,13 @@ int orc_run_gated(orc_film *f, double T, int32_t h_num, int32_t hs_num, uint32_t
     if (rec)
         *rec = r;
     return 0;
+}
+
+/* n_sweeps sweeps at (T, h_num) behind the switching-field gate of hs_num. */
+int orc_run_gated(orc_film *f, double T, int32_t h_num, int32_t hs_num, uint32_t n_sweeps, uint32_t n_discard,
+                  orc_record *rec)
+{
+    return orc_run_full(f, T, h_num, hs_num, 0, n_sweeps, n_discard, rec);
 }
 
 /* n_sweeps sweeps at (T, h_num) without the gate (steps 1-3 only). */

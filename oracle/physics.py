@@ -44,3 +44,14 @@ def single_spin_magnetisation(H: float, T: float) -> float:
 def critical_concentration(z: float) -> float:
     """Eq. (2): p_c = 2 / z for mean coordination z."""
     return 2.0 / z
+
+
+def two_free_spins_with_anisotropy(H: float, h_an: float, T: float):
+    """Two spins without a bond in field H with the anisotropy term -h_an |M| of Eq. (7).
+
+    The four states have E(++) = -2H - 2 h_an, E(--) = 2H - 2 h_an and E(+-) = E(-+) = 0, so
+    <M> = 2 sinh(2H/T) / (cosh(2H/T) + exp(-2 h_an/T)) and
+    <|M|> = 2 cosh(2H/T) / (cosh(2H/T) + exp(-2 h_an/T)).  Returns (<M>, <|M|>).
+    """
+    c, s, e = math.cosh(2.0 * H / T), math.sinh(2.0 * H / T), math.exp(-2.0 * h_an / T)
+    return 2.0 * s / (c + e), 2.0 * c / (c + e)

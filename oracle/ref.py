@@ -8,6 +8,8 @@ Contents:
   philox4x32_10      -- Philox4x32-10 (Salmon et al., SC 2011) on Python ints
   threshold          -- Eq. (8) threshold floor(2^32 exp(-(q/10)/T)) via math.exp
   gate_threshold     -- Eq. (9) switching-field gate floor(2^32 exp(-|h_s|/T)), h_s = hs_num/20
+  anisotropy_q       -- the change of the anisotropy energy -h_an |M| of Eq. (7)
+                        for one flip, in tenths
   TinyFilm           -- the sweep of Section 5 (steps 1-3) on a site list
   enumerate_exact    -- partition function of Eq. (4) and Gibbs averages of
                         Eq. (5) by enumerating all 2^N configurations
@@ -70,6 +72,17 @@ def accept_probability(q: int, T: float, quantised: bool = True) -> float:
     if quantised:
         return threshold(q, T) / 2.0**32
     return math.exp(-(q / 10.0) / T)
+
+
+def anisotropy_energy(M: int, an_num: int) -> float:
+    """Anisotropy term of Eq. (7), -h_an |M| with h_an = an_num / 20."""
+    return -(an_num / 20.0) * abs(M)
+
+
+def anisotropy_q(M: int, s: int, an_num: int) -> int:
+    """10 (E_an(M - 2s) - E_an(M)): the anisotropy part of q when spin s flips
+    while the magnetisation is M.  |M - 2s| - |M| is even, so this is an integer."""
+    return -(an_num * (abs(M - 2 * s) - abs(M))) // 2
 
 
 class TinyFilm:
@@ -139,19 +152,22 @@ class TinyFilm:
     def bond_energy(self) -> int:
         return -sum(self.s[i] * self.s[j] for i, j in self.bonds)
 
-    def sweep(self, T: float, h_num: int, hs_num: int = 0) -> int:
+    def sweep(self, T: float, h_num: int, hs_num: int = 0, an_num: int = 0) -> int:
         """One sweep; with hs_num != 0 each attempt first passes the switching-field
-        gate of Eq. (9) (steps 4-5 of Section 5) with its own draw (tag 2)."""
+        gate of Eq. (9) (steps 4-5 of Section 5) with its own draw (tag 2).  With
+        an_num != 0 the anisotropy term of Eq. (7) enters with M frozen at its
+        value when the sublattice's phase starts."""
         acc = 0
         g = gate_threshold(hs_num, T)
         for sigma in range(4):
+            M = self.magnetisation()
             for i in range(self.N):
                 if self.sub[i] != sigma:
                     continue
                 if g != M32 and not self.draw(i, self.t, 2) < g:
                     continue
                 n = sum(self.s[j] for j in self.nbrs[i])
-                q = self.s[i] * (20 * n + h_num)
+                q = self.s[i] * (20 * n + h_num) + anisotropy_q(M, self.s[i], an_num)
                 if q <= 0 or self.draw(i, self.t, 0) < threshold(q, T):
                     self.s[i] = -self.s[i]
                     acc += 1
@@ -159,8 +175,9 @@ class TinyFilm:
         return acc
 
 
-def enumerate_exact(film: TinyFilm, T: float, h_num: int):
-    """Exact Gibbs averages over all 2^N configurations (Eqs. 4-5 with J = k = 1, H = h_num/20).
+def enumerate_exact(film: TinyFilm, T: float, h_num: int, an_num: int = 0):
+    """Exact Gibbs averages over all 2^N configurations (Eqs. 4-5 with J = k = 1, H = h_num/20,
+    and the anisotropy term -h_an |M| of Eq. (7) with h_an = an_num/20).
 
     Returns dict with Z (partition function), <M>, <M^2>, <|M|>, <E_bond>, <E_total>.
     """
@@ -174,7 +191,7 @@ def enumerate_exact(film: TinyFilm, T: float, h_num: int):
     for i, j in film.bonds:
         Eb -= spins[:, i] * spins[:, j]
     H = h_num / 20.0
-    E = Eb - H * M
+    E = Eb - H * M - (an_num / 20.0) * np.abs(M)
     w = np.exp(-(E - E.min()) / T)
     Zp = w.sum()
     p = w / Zp
@@ -188,22 +205,23 @@ def enumerate_exact(film: TinyFilm, T: float, h_num: int):
     }
 
 
-def boltzmann(film: TinyFilm, T: float, h_num: int) -> Tuple[List[Tuple[int, ...]], np.ndarray]:
+def boltzmann(film: TinyFilm, T: float, h_num: int, an_num: int = 0) -> Tuple[List[Tuple[int, ...]], np.ndarray]:
     states = list(itertools.product((-1, 1), repeat=film.N))
     H = h_num / 20.0
     E = []
     for st in states:
         eb = -sum(st[i] * st[j] for i, j in film.bonds)
-        E.append(eb - H * sum(st))
+        E.append(eb - H * sum(st) + anisotropy_energy(sum(st), an_num))
     E = np.array(E)
     w = np.exp(-(E - E.min()) / T)
     return states, w / w.sum()
 
 
 def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bool = True,
-                 hs_num: int = 0) -> np.ndarray:
+                 hs_num: int = 0, an_num: int = 0) -> np.ndarray:
     """Transition matrix of one sublattice phase: its sites are updated independently;
-    a site flips if its switching-field gate (probability g) and the Metropolis test pass."""
+    a site flips if its switching-field gate (probability g) and the Metropolis test pass.
+    The anisotropy term sees the magnetisation of the state the phase starts from."""
     g = gate_probability(hs_num, T, quantised)
     states = list(itertools.product((-1, 1), repeat=film.N))
     idx = {st: a for a, st in enumerate(states)}
@@ -212,9 +230,11 @@ def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bo
     for a, st in enumerate(states):
         # each member flips independently with its own acceptance probability
         probs = []
+        M = sum(st)
         for i in members:
             n = sum(st[j] for j in film.nbrs[i])
-            probs.append(g * accept_probability(st[i] * (20 * n + h_num), T, quantised))
+            q = st[i] * (20 * n + h_num) + anisotropy_q(M, st[i], an_num)
+            probs.append(g * accept_probability(q, T, quantised))
         for flips in itertools.product((0, 1), repeat=len(members)):
             pr = 1.0
             new = list(st)
@@ -226,8 +246,9 @@ def phase_matrix(film: TinyFilm, T: float, h_num: int, sigma: int, quantised: bo
     return P
 
 
-def sweep_matrix(film: TinyFilm, T: float, h_num: int, quantised: bool = True, hs_num: int = 0) -> np.ndarray:
+def sweep_matrix(film: TinyFilm, T: float, h_num: int, quantised: bool = True, hs_num: int = 0,
+                 an_num: int = 0) -> np.ndarray:
     P = np.eye(2**film.N)
     for sigma in range(4):
-        P = P @ phase_matrix(film, T, h_num, sigma, quantised, hs_num)
+        P = P @ phase_matrix(film, T, h_num, sigma, quantised, hs_num, an_num)
     return P

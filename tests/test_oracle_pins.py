@@ -571,3 +571,184 @@ def test_surface_image_c_matches_python(oracle_lib, seed):
         cf.run(T, hn, 3)
         np.testing.assert_array_equal(cf.surface_image(), tf.surface_image())
     assert cf.film_stats()["mean_coordination"] == pytest.approx(tf.mean_coordination(), abs=1e-12)
+
+
+# --------------------------------------------------------------------------- anisotropy (Eq. 7)
+# The anisotropy term -h_an |M| couples every site to the global M; the oracle
+# freezes M at the start of each sublattice phase.  On films with at most one
+# site per sublattice this is serial Metropolis on the Hamiltonian of Eq. (7),
+# whose Gibbs measure is then stationary; that, closed forms and symmetries
+# pin the term's sign and its cases (|M| >= 2, M = 0, M = +-1).
+_ANISO_CASES = ((1.5, 10, 30), (3.0, -40, 15), (0.7, 0, 8), (2.0, 5, 50))
+
+
+def test_anisotropy_q_cases():
+    """|M| >= 2: a flip of s changes q by h_an sign(M) s (an extra field along M);
+    a flip that raises |M| from 0 or 1 lowers q by an_num; one that lowers |M| from 1 leaves it."""
+    for a in (0, 7, 40):
+        for M in range(-9, 10):
+            for s in (-1, 1):
+                q = ref.anisotropy_q(M, s, a)
+                if abs(M) >= 2:
+                    assert q == a * s * (1 if M > 0 else -1)
+                elif abs(M - 2 * s) > abs(M):
+                    assert q == -a
+                else:
+                    assert q == 0
+
+
+def test_anisotropy_transition_matrices():
+    for (h, Z) in _pair_and_triangle():
+        film = ref.TinyFilm(h, Z)
+        for T, hn, an in _ANISO_CASES:
+            states, pi = ref.boltzmann(film, T, hn, an)
+            _, pi0 = ref.boltzmann(film, T, hn)
+            assert np.max(np.abs(pi - pi0)) > 1e-3  # the term matters here
+            for sigma in range(4):
+                for quant, tol in ((False, 1e-15), (True, 2.0**-31)):
+                    P = ref.phase_matrix(film, T, hn, sigma, quantised=quant, an_num=an)
+                    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-15)
+                    flow = pi[:, None] * P
+                    assert np.max(np.abs(flow - flow.T)) <= tol
+            S = ref.sweep_matrix(film, T, hn, quantised=False, an_num=an)
+            assert np.max(np.abs(pi @ S - pi)) <= 1e-14
+
+
+def test_anisotropy_transition_frequencies_sampled(oracle_lib):
+    """One-sweep frequencies of the C oracle with anisotropy against the quantised sweep matrix."""
+    h, Z = _pair_and_triangle()[1]
+    film = ref.TinyFilm(h, Z)
+    T, hn, an = 2.5, -5, 40
+    S = ref.sweep_matrix(film, T, hn, quantised=True, an_num=an)
+    S0 = ref.sweep_matrix(film, T, hn, quantised=True)
+    states = [tuple(s) for s in __import__("itertools").product((-1, 1), repeat=film.N)]
+    idx = {s: a for a, s in enumerate(states)}
+    start = (1, -1, -1)  # M = -1 when the first phase starts
+    assert np.max(np.abs(S[idx[start]] - S0[idx[start]])) > 0.2  # the term changes this row
+    f = cpu.Film(h, Z, seed=5151, replica=7)
+    cube = np.zeros((Z, 4, 4), dtype=np.int8)
+    for i, (x, y, z) in enumerate(film.sites):
+        cube[z, y, x] = start[i]
+    nsamp = 60000
+    counts = np.zeros(len(states))
+    for t in range(nsamp):
+        f.set_spins(cube, t)
+        f.run(T, hn, 1, 0, 0, an)
+        sp = f.spins()
+        counts[idx[tuple(int(sp[z, y, x]) for (x, y, z) in film.sites)]] += 1
+    p = S[idx[start]]
+    sd = np.sqrt(nsamp * p * (1 - p)) + 1e-9
+    assert np.all(np.abs(counts - nsamp * p) <= 5 * sd + 1), (counts, nsamp * p)
+    assert counts[p == 0].sum() == 0
+
+
+def test_anisotropy_two_free_spins_closed_form(oracle_lib):
+    """Two unbonded spins in different sublattices: the C oracle's long-run <M> and <|M|>
+    against the closed form of the Gibbs measure of Eq. (7)."""
+    h = np.zeros((8, 8), dtype=np.uint8)
+    h[0, 0] = 1   # (0, 0, 0), sublattice 0
+    h[3, 3] = 1   # (3, 3, 0), sublattice 1, not a neighbour
+    T, hn, an = 1.0, 5, 10
+    f = cpu.Film(h, 1, seed=31, init=cpu.INIT_UP)
+    assert f.state()[2] == 2 and f.state()[3] == 0
+    m_ex, a_ex = physics.two_free_spins_with_anisotropy(hn / 20, an / 20, T)
+    m_free, _ = physics.two_free_spins_with_anisotropy(hn / 20, 0.0, T)
+    assert abs(m_ex - m_free) > 0.15
+    nblk, blk = 40, 20000
+    ms, As = [], []
+    for _ in range(nblk):
+        r = f.run(T, hn, blk, 0, 0, an)
+        ms.append(r.sum_M / blk)
+        As.append(r.sum_absM / blk)
+    for vals, ex in ((ms, m_ex), (As, a_ex)):
+        se = np.std(vals, ddof=1) / math.sqrt(nblk)
+        assert abs(np.mean(vals) - ex) <= 5 * se + 1e-4, (np.mean(vals), ex)
+
+
+def test_anisotropy_exact_enumeration(oracle_lib):
+    """Triangle (one site per sublattice): time averages of the C oracle equal the Gibbs
+    averages of the Hamiltonian of Eq. (7) by exact enumeration."""
+    h, Z = _pair_and_triangle()[1]
+    tf = ref.TinyFilm(h, Z)
+    T, hn, an = 2.0, 6, 24
+    ex = ref.enumerate_exact(tf, T, hn, an)
+    ex0 = ref.enumerate_exact(tf, T, hn)
+    assert abs(ex["absM"] - ex0["absM"]) > 0.1
+    f = cpu.Film(h, Z, seed=0xA11, replica=2)
+    f.run(T, hn, 1000, 0, 0, an)
+    nblk, blk = 40, 10000
+    ms, As = [], []
+    for _ in range(nblk):
+        r = f.run(T, hn, blk, 0, 0, an)
+        ms.append(r.sum_M / blk)
+        As.append(r.sum_absM / blk)
+    for vals, key in ((ms, "M"), (As, "absM")):
+        se = float(np.std(vals, ddof=1) / math.sqrt(nblk))
+        assert abs(float(np.mean(vals)) - ex[key]) <= 5.0 * se + 1e-3, (key, np.mean(vals), ex[key])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_anisotropy_c_oracle_matches_python_oracle(oracle_lib, seed):
+    rng = np.random.default_rng(700 + seed)
+    Y, X, Z = [(8, 8, 3), (6, 10, 4)][seed]
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    key = int(rng.integers(0, 2**63))
+    tf = ref.TinyFilm(h, Z, seed=key, replica=seed)
+    tf.init_random()
+    cf = cpu.Film(h, Z, key, seed, init=cpu.INIT_RANDOM)
+    for T, hn, hs, an in ((2.5, 20, 0, 40), (1.1, -7, 160, 12), (6.0, 0, 0, 100), (0.9, 55, 3, 5),
+                          (4.0, -30, 0, 60)):
+        acc = sum(tf.sweep(T, hn, hs, an) for _ in range(4))
+        r = cf.run(T, hn, 4, 0, hs, an)
+        sp = cf.spins()
+        assert all(sp[z, y, x] == tf.s[i] for i, (x, y, z) in enumerate(tf.sites))
+        assert r.M == tf.magnetisation() and r.E == tf.bond_energy() and r.accepted == acc
+
+
+@pytest.mark.parametrize("init", [cpu.INIT_UP, cpu.INIT_RANDOM])
+def test_anisotropy_field_reversal_symmetry(oracle_lib, init):
+    """The term is even in M, so H -> -H with all spins reversed mirrors the run bit for bit."""
+    rng = np.random.default_rng(6)
+    h = rng.integers(0, 5, size=(24, 16)).astype(np.uint8)
+    a = cpu.Film(h, 4, seed=778, replica=3, init=init)
+    b = cpu.Film(h, 4, seed=778, replica=3, init=cpu.INIT_DOWN)
+    b.set_spins(-a.spins(), 0)
+    for hn, an in ((40, 20), (10, 60), (-20, 5), (-60, 200), (0, 30), (33, 1)):
+        ra = a.run(3.5, hn, 3, 0, 0, an).as_tuple()
+        rb = b.run(3.5, -hn, 3, 0, 0, an).as_tuple()
+        assert np.array_equal(b.spins(), -a.spins())
+        assert rb == (-ra[0], ra[1], -ra[2], ra[3], ra[4], ra[5])
+
+
+def test_anisotropy_is_a_field_shift_while_the_excess_lasts(oracle_lib):
+    """With |M| >= 2 at every phase start the term acts as the field h_an sign(M): the run
+    equals the run without it at h_num + an_num sign(M), bit for bit."""
+    rng = np.random.default_rng(10)
+    h = rng.integers(0, 5, size=(32, 32)).astype(np.uint8)
+    for init, sign in ((cpu.INIT_UP, 1), (cpu.INIT_DOWN, -1)):
+        a = cpu.Film(h, 4, seed=55, init=init)
+        b = cpu.Film(h, 4, seed=55, init=init)
+        N = a.state()[2]
+        for _ in range(15):
+            ra = a.run(2.0, 4 * sign, 1, 0, 0, 30)
+            rb = b.run(2.0, 4 * sign + 30 * sign, 1)
+            assert ra.as_tuple() == rb.as_tuple()
+            assert np.array_equal(a.spins(), b.spins())
+            # M far from 0: no phase can reach |M| < 2
+            assert sign * ra.M > N // 2
+        assert ra.accepted > 0
+
+
+def test_anisotropy_supports_the_spin_excess_at_low_temperature(oracle_lib):
+    """T -> 0, free spins magnetised up in a reversed field: with h_an > |H| the excess holds
+    (the move costs 2 (h_an - |H|) > 0), without the term every spin flips in the first sweep."""
+    h = np.zeros((8, 8), dtype=np.uint8)
+    for (y, x) in ((0, 0), (3, 3), (4, 0), (0, 4), (6, 2), (3, 5)):
+        h[y, x] = 1
+    f = cpu.Film(h, 1, seed=3, init=cpu.INIT_UP)
+    N, n_bonds = f.state()[2], f.state()[3]
+    assert N == 6 and n_bonds == 0
+    r = f.run(1e-3, -10, 5, 0, 0, 20)
+    assert r.M == N and r.accepted == 0
+    r = f.run(1e-3, -10, 1, 0, 0, 0)
+    assert r.M == -N and r.accepted == N
