@@ -33,12 +33,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def plain_steps(cfg, first, count, hs_num=0):
+def plain_steps(cfg, first, count, hs_num=0, an_num=0):
     hn = cfg.h_nums
-    return [(cfg.T, hn[(first + i) % len(hn)], cfg.sweeps_per_step, 0, hs_num) for i in range(count)]
+    return [(cfg.T, hn[(first + i) % len(hn)], cfg.sweeps_per_step, 0, hs_num, an_num) for i in range(count)]
 
 
-def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0):
+def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0, an_num=0):
     import torch
 
     from paper_1205_5588_amd.lattice import Lattice
@@ -50,13 +50,13 @@ def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0):
         lat.set_tuning(*tuning)
     n_occ = lat.observables()["n_occ"]
     if warmup:
-        lat.run_schedule(plain_steps(cfg, 0, warmup, hs_num))
+        lat.run_schedule(plain_steps(cfg, 0, warmup, hs_num, an_num))
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(lat.stream)
-    recs = lat.run_schedule(plain_steps(cfg, warmup, steps, hs_num))
+    recs = lat.run_schedule(plain_steps(cfg, warmup, steps, hs_num, an_num))
     ev1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -351,6 +351,17 @@ def main():
                           "accepted_per_attempt": round(float(recs_g[:, 5].sum()) / (n_occ_g * sw_g), 5)}
         log("gated:", extra["gated"])
         del lat_g
+        # the same ramp with the anisotropy term of Eq. 7, h_an = 2 (an_num = 40), on the
+        # per-sublattice kernels (M frozen per phase)
+        an_tl = (64, 4, 2, True, 0)
+        lat_a, n_occ_a, sw_a, wall_a, gpu_ms_a, recs_a = bench_plain(cfg, h, 0, min(args.steps, 40), 2, an_tl,
+                                                                     an_num=40)
+        extra["anisotropy"] = {"value": round(n_occ_a * sw_a / (gpu_ms_a * 1e-3), 1),
+                               "unit": "spin-flip attempts/s", "steps": min(args.steps, 40), "an_num": 40,
+                               "tiling": list(an_tl[:3]), "kernel": "k_phase_i8",
+                               "ms_per_sweep": round(gpu_ms_a / sw_a, 5)}
+        log("anisotropy:", extra["anisotropy"])
+        del lat_a
         extra["batched"] = bench_batched(args)
         log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
         if not args.no_serve:

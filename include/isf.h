@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define ISF_ABI_VERSION 1
+#define ISF_ABI_VERSION 2
 
 enum {
     ISF_OK = 0,
@@ -99,6 +99,14 @@ typedef struct {
                            |hs_num| <= 200000; a site may flip only if its gate draw (Philox tag 2) is below
                            floor(2^32 exp(-|h_s|/T)) and the Metropolis test passes; 0: no gate.  INT8
                            films only (EINVAL for a bit-packed film) */
+    int32_t an_num;     /* anisotropy field of Eq. 7 (Section 5): the energy gains -h_an |M| with
+                           h_an = an_num / 20, 0 <= an_num <= 200000; 0: no anisotropy.  M couples every
+                           site, so it is frozen at its value when each sublattice phase starts: a flip of
+                           spin S changes q by -an_num (|M - 2S| - |M|) / 2 with that M (an extra field
+                           h_an sign(M) while |M| >= 2).  INT8 films on the per-sublattice kernels
+                           (ISF_KERNEL_TILES or _LIST) of a single lattice: isf_schedule_load returns
+                           EINVAL for a bit-packed film or a whole-sweep tuning, and isf_batch_advance
+                           refuses a lattice whose loaded schedule has it */
 } isf_step;
 
 typedef struct {

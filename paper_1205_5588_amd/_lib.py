@@ -38,7 +38,7 @@ class Record(ctypes.Structure):
 
 class Step(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("h_num", ctypes.c_int32), ("n_sweeps", ctypes.c_uint32),
-                ("n_discard", ctypes.c_uint32), ("hs_num", ctypes.c_int32)]
+                ("n_discard", ctypes.c_uint32), ("hs_num", ctypes.c_int32), ("an_num", ctypes.c_int32)]
 
 
 class FilmStats(ctypes.Structure):

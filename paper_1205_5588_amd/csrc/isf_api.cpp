@@ -27,6 +27,7 @@ bool tiling_supported(const Tiling &tl);
 hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
 hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s);
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
+hipError_t launch_aniso_stage(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 const uint8_t *lists, uint32_t q, hipStream_t s);
 hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
@@ -164,6 +165,18 @@ uint32_t gate_threshold_of(int32_t hs, double T) {
     return (uint32_t)std::floor(std::ldexp(p, 32));
 }
 
+// Thresholds of q + an (words [0, 50)) and q - an (words [50, 100)), q = s (20 n + h),
+// for the anisotropy of Eq. (7); see k_aniso_stage for which half is used when.
+void aniso_table_of(double T, int32_t h, int32_t an, uint32_t *out /* kAnWords */) {
+    for (int si = 0; si < 2; ++si) {
+        const int s = si ? 1 : -1;
+        for (int n = -12; n <= 12; ++n) {
+            out[si * 25 + n + 12] = threshold_of(s * (20 * n + h) + an, T);
+            out[50 + si * 25 + n + 12] = threshold_of(s * (20 * n + h) - an, T);
+        }
+    }
+}
+
 void table_of(double T, int32_t h, int32_t hs, uint32_t *out /* kTableWords */) {
     for (int si = 0; si < 2; ++si) {
         const int s = si ? 1 : -1;
@@ -212,6 +225,9 @@ struct isf_lattice {
     // a run of whole-sweep launches is open: the schedule position lives in the
     // parity-buffered positions until k_whole_flush hands it back
     bool whole_active;
+    // the loaded schedule has the anisotropy term: every phase is preceded by
+    // the launch that stages its thresholds
+    bool aniso;
 };
 
 struct isf_batch {
@@ -336,6 +352,11 @@ int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
             continue;
         }
         for (uint32_t s = 0; s < 4; ++s) {
+            if (lat->aniso) {
+                hipError_t e = launch_aniso_stage(lat->L, lat->stream);
+                if (e != hipSuccess)
+                    return fail(ISF_EHIP, "anisotropy launch failed: %s", hipGetErrorString(e));
+            }
             int32_t rc = launch_phase(lat, s);
             if (rc)
                 return rc;
@@ -486,6 +507,8 @@ int32_t validate_steps(const isf_step *steps, uint32_t n) {
             return fail(ISF_EINVAL, "step %u: n_discard > n_sweeps", i);
         if (steps[i].hs_num > 200000 || steps[i].hs_num < -200000)
             return fail(ISF_EINVAL, "step %u: |hs_num| = %d exceeds 200000", i, steps[i].hs_num);
+        if (steps[i].an_num > 200000 || steps[i].an_num < 0)
+            return fail(ISF_EINVAL, "step %u: an_num = %d outside [0, 200000]", i, steps[i].an_num);
     }
     return ISF_OK;
 }
@@ -580,6 +603,7 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     L.slots = reinterpret_cast<Slot *>(lat->aux_dev + al.off_slots);
     L.steps = reinterpret_cast<StepDesc *>(lat->aux_dev + al.off_steps);
     L.tables = reinterpret_cast<uint32_t *>(lat->aux_dev + al.off_tables);
+    L.atables = reinterpret_cast<uint32_t *>(lat->aux_dev + al.off_atables);
     L.records = reinterpret_cast<isf_record *>(lat->aux_dev + al.off_records);
     L.pos = reinterpret_cast<SweepPos *>(lat->aux_dev + al.off_pos);
     L.slots2 = reinterpret_cast<Slot *>(lat->aux_dev + al.off_slots2);
@@ -675,6 +699,8 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
         if (!ok)
             return fail(ISF_EINVAL, "unsupported tiling %ux%ux%u", tl.tx, tl.ty, tl.ry);
     }
+    if (lat->aniso && is_whole(tl.kernel))
+        return fail(ISF_EINVAL, "the loaded schedule has the anisotropy term, which needs the per-sublattice kernels");
     lat->tiling = tl;
     lat->use_graph = t->use_graph != 0;
     return ISF_OK;
@@ -801,13 +827,29 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
         return rc;
     std::vector<StepDesc> sd(n ? n : 1);
     std::vector<uint32_t> tabs((size_t)(n ? n : 1) * kTableWords, 0);
+    bool aniso = false;
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) {
         sd[i] = StepDesc{steps[i].n_sweeps, steps[i].n_discard};
         if (steps[i].hs_num != 0 && lat->d.format != ISF_FORMAT_INT8)
             return fail(ISF_EINVAL, "step %u: the switching-field gate needs an INT8 film", i);
+        if (steps[i].an_num != 0) {
+            if (lat->d.format != ISF_FORMAT_INT8)
+                return fail(ISF_EINVAL, "step %u: the anisotropy term needs an INT8 film", i);
+            if (is_whole(lat->tiling.kernel))
+                return fail(ISF_EINVAL,
+                            "step %u: the anisotropy term needs the per-sublattice kernels (tuning kernel TILES "
+                            "or LIST)", i);
+            aniso = true;
+        }
         table_of(steps[i].T, steps[i].h_num, steps[i].hs_num, &tabs[(size_t)i * kTableWords]);
         total += steps[i].n_sweeps;
+    }
+    std::vector<uint32_t> atabs;
+    if (aniso) {
+        atabs.assign((size_t)n * kAnWords, 0);
+        for (uint32_t i = 0; i < n; ++i)
+            aniso_table_of(steps[i].T, steps[i].h_num, steps[i].an_num, &atabs[(size_t)i * kAnWords]);
     }
     struct {
         uint32_t step, sweep_in_step;
@@ -821,10 +863,16 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
                                hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, cur_table), tabs.data(),
                                sizeof(uint32_t) * kTableWords, hipMemcpyHostToDevice, lat->stream));
+        if (aniso)
+            HIP_TRY(hipMemcpyAsync(lat->L.atables, atabs.data(), sizeof(uint32_t) * kAnWords * n,
+                                   hipMemcpyHostToDevice, lat->stream));
     }
     HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, step), &mid, sizeof mid, hipMemcpyHostToDevice,
                            lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
+    if (aniso != lat->aniso)
+        drop_graph(lat);  // a cached graph holds the staging launches or not
+    lat->aniso = aniso;
     lat->sched_steps = n;
     lat->sched_total = total;
     lat->sched_enqueued = 0;
@@ -1363,6 +1411,8 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
             return fail(ISF_EINVAL, "null lattice %u", i);
         if (lats[i]->d.format != format)
             return fail(ISF_ESTATE, "lattices of a batch must share one format");
+        if (lats[i]->aniso)
+            return fail(ISF_EINVAL, "lattice %u: batches do not run the anisotropy term", i);
     }
     if (mode == ISF_BATCH_WHOLE)
         return batch_advance_whole(b, lats, n, max_sweeps, enqueued_out);

@@ -28,6 +28,9 @@ namespace isf {
 constexpr uint32_t kSlots = 64;          // spread of the per-sweep atomic accumulators
 constexpr uint32_t kTableWords = 52;     // 50 thresholds, the gate threshold, padding
 constexpr uint32_t kGateWord = 50;       // switching-field gate threshold (kSentinel: no gate)
+// Anisotropy thresholds of one step: words [0, 50) hold the thresholds of
+// q + an_num and words [50, 100) those of q - an_num, in the table's order.
+constexpr uint32_t kAnWords = 100;
 constexpr uint32_t kDefaultMaxSteps = 1024;
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 
@@ -85,6 +88,7 @@ struct LatDev {
     Slot *slots;          // [kSlots]
     StepDesc *steps;      // [max_steps]
     uint32_t *tables;     // [max_steps][kTableWords]
+    uint32_t *atables;    // [max_steps][kAnWords]
     isf_record *records;  // [max_steps]
     uint32_t X, Y, Z;
     uint32_t W;           // compact sites per row = X/2
@@ -105,7 +109,7 @@ struct LatDev {
 
 // Aux buffer layout.
 struct AuxLayout {
-    uint64_t off_state, off_slots, off_steps, off_tables, off_records, off_pos, off_slots2, total;
+    uint64_t off_state, off_slots, off_steps, off_tables, off_atables, off_records, off_pos, off_slots2, total;
 };
 
 inline AuxLayout aux_layout(uint32_t max_steps) {
@@ -117,7 +121,8 @@ inline AuxLayout aux_layout(uint32_t max_steps) {
     a.off_slots = up(sizeof(DevState), 4096);
     a.off_steps = up(a.off_slots + sizeof(Slot) * kSlots, 4096);
     a.off_tables = up(a.off_steps + sizeof(StepDesc) * max_steps, 256);
-    a.off_records = up(a.off_tables + sizeof(uint32_t) * kTableWords * max_steps, 256);
+    a.off_atables = up(a.off_tables + sizeof(uint32_t) * kTableWords * max_steps, 256);
+    a.off_records = up(a.off_atables + sizeof(uint32_t) * kAnWords * max_steps, 256);
     a.off_pos = up(a.off_records + sizeof(isf_record) * max_steps, 4096);
     a.off_slots2 = up(a.off_pos + 2 * sizeof(SweepPos), 4096);
     a.total = up(a.off_slots2 + sizeof(Slot) * kSlots, 256);

@@ -174,6 +174,50 @@ __global__ __launch_bounds__(64) void k_sweep_end_batch(const BatchEntry *__rest
 }
 
 // --------------------------------------------------------------------------
+// Anisotropy of Eq. (7), -h_an |M| (Section 5), with M frozen at the start of
+// each sublattice phase.  Launched (one wave) before every phase of a
+// schedule with the term: it forms the phase's M from the state's M (the end
+// of the previous sweep) and this sweep's slots (the phases already done),
+// and writes the thresholds of the full q into the current table, where the
+// phase kernels read them.  A flip of spin s changes q by
+// -an (|M - 2s| - |M|) / 2, so each half of the table (s = -1, s = +1) is the
+// table of q + an, of q, or of q - an:
+//   M >= 2: s = +1 from q + an, s = -1 from q - an (a field h_an along M);
+//   M <= -2: s = +1 from q - an, s = -1 from q + an;
+//   M = 0: both from q - an (either flip raises |M|);
+//   M = 1: s = +1 from q (|M| falls to 1), s = -1 from q - an;
+//   M = -1: s = +1 from q - an, s = -1 from q.
+// The gate threshold (word kGateWord) is left as it is.
+__global__ __launch_bounds__(64) void k_aniso_stage(LatDev L) {
+    const uint32_t lane = threadIdx.x;
+    int64_t dM = 0;
+    for (uint32_t s = lane; s < kSlots; s += 64)
+        dM += L.slots[s].dM;
+    dM = wave_sum(dM);
+    DevState *st = L.st;
+    const uint32_t step = st->step;
+    if (step >= st->n_steps || lane >= 50)
+        return;
+    const int64_t M = st->M + dM;
+    const bool up = lane >= 25;  // the half of the table for s = +1
+    // 0: q, 1: q + an, 2: q - an
+    uint32_t src;
+    if (M >= 2)
+        src = up ? 1u : 2u;
+    else if (M <= -2)
+        src = up ? 2u : 1u;
+    else if (M == 0)
+        src = 2u;
+    else if (M == 1)
+        src = up ? 0u : 2u;
+    else
+        src = up ? 2u : 0u;
+    const uint32_t v = src == 0u ? L.tables[(size_t)step * kTableWords + lane]
+                                 : L.atables[(size_t)step * kAnWords + (src == 1u ? 0u : 50u) + lane];
+    st->cur_table[lane] = v;
+}
+
+// --------------------------------------------------------------------------
 // Start: occupied sites get +1, -1, or +1 iff their INIT draw is below 2^31
 // (counter word 3 = sigma + 4, sweep word 0).  Vacancies keep the byte 1.
 __global__ void k_init_i8(LatDev L, int32_t mode) {
@@ -286,6 +330,11 @@ hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, ui
 
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(64), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_aniso_stage(const LatDev &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_aniso_stage, dim3(1), dim3(64), 0, s, L);
     return hipGetLastError();
 }
 

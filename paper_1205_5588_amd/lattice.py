@@ -48,12 +48,14 @@ def lattice_bytes(X: int, Y: int, Z: int, fmt: int = FORMAT_INT8) -> Tuple[int, 
 
 
 def make_steps(steps: Sequence[Tuple]):
-    """steps: (T, h_num, n_sweeps, n_discard[, hs_num]) each; hs_num = 0 (no switching-field gate) if absent."""
+    """steps: (T, h_num, n_sweeps, n_discard[, hs_num[, an_num]]) each; hs_num = 0 (no switching-field
+    gate) and an_num = 0 (no anisotropy) if absent."""
     arr = (Step * max(1, len(steps)))()
     for i, st in enumerate(steps):
         T, h, n, nd = st[:4]
         hs = st[4] if len(st) > 4 else 0
-        arr[i] = Step(float(T), int(h), int(n), int(nd), int(hs))
+        an = st[5] if len(st) > 5 else 0
+        arr[i] = Step(float(T), int(h), int(n), int(nd), int(hs), int(an))
     return arr
 
 
@@ -138,7 +140,7 @@ class Lattice:
 
     # ------------------------------------------------------------------ runs
     def run_schedule(self, steps: Sequence[Tuple[float, int, int, int]]) -> np.ndarray:
-        """steps: (T, h_num, n_sweeps, n_discard[, hs_num]) each; returns int64 [n, 6] records."""
+        """steps: (T, h_num, n_sweeps, n_discard[, hs_num[, an_num]]) each; returns int64 [n, 6] records."""
         n = len(steps)
         arr = make_steps(steps)
         out = (Record * max(1, n))()

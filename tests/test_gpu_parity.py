@@ -686,3 +686,81 @@ def test_surface_image_of_the_ramp_film(isf):
 
         small = torch.empty(10, dtype=torch.int8, device="cuda")
         g.surface_image(out=small)
+
+
+# ------------------------------------------------------------------ anisotropy (Eq. 7)
+# (T, h_num, n_sweeps, n_discard, hs_num, an_num); the last step has no anisotropy
+ANISO_STEPS = [(2.5, 30, 7, 0, 0, 40), (3.5, -45, 6, 1, 0, 160), (4.5, 0, 9, 2, 0, 20), (3.0, -7, 6, 0, 40, 60),
+               (1e-3, 241, 2, 0, 0, 20), (2.0, -20, 66, 3, 7, 30), (4.0, 0, 5, 0, 0, 0)]
+
+
+@pytest.mark.parametrize("kernel,tiling,graph", [(0, (64, 4, 2), True), (0, (16, 16, 1), False),
+                                                 (0, (32, 8, 4), True), (1, (64, 4, 1), True)])
+@pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1), (16, 8, 2)])
+def test_aniso_schedule_matches_oracle(isf, kernel, tiling, graph, X, Y, Z):
+    h = _rand_h((Y, X), Z, 13 * X + Y + Z)
+    g, o = _pair(isf, h, Z, 24680, replica=5, init=2)
+    if kernel == 1:
+        g.attach_items()
+    g.set_tuning(tiling[0], tiling[1], tiling[2], graph, kernel)
+    _say("aniso schedule", kernel, tiling, graph, X, Y, Z)
+    np.testing.assert_array_equal(g.run_schedule(ANISO_STEPS), np.array([o.run(*s).as_tuple() for s in ANISO_STEPS]))
+    _assert_same(g, o)
+
+
+@pytest.mark.parametrize("X,Y,Z,hseed,T", [(8, 4, 1, 25, 6.0), (16, 8, 2, 1, 12.0)])
+def test_aniso_through_small_magnetisation(isf, X, Y, Z, hseed, T):
+    """Hot small films at H = 0 pass through M = 0 (even site count) or M = +-1 (odd), the cases
+    where the term is not a field."""
+    h = _rand_h((Y, X), Z, hseed)
+    g, o = _pair(isf, h, Z, 1234567, replica=2, init=2)
+    steps = [(T, 0, 1, 0, 0, 20)] * 120 + [(T - 1.0, 3, 1, 0, 30, 45)] * 80
+    _say("aniso small M", X, Y, Z)
+    rg = g.run_schedule(steps)
+    np.testing.assert_array_equal(rg, np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+    assert np.any(np.abs(rg[:, 0]) == o.state()[2] % 2)
+
+
+def test_aniso_large_film_prefix(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.set_tuning(64, 4, 2, True, 0)
+    _say("aniso large film prefix")
+    steps = [(c.T, hn, 3, 0, 0, 40) for hn in (120, 0, -60)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+def test_aniso_rejected_where_unsupported(isf):
+    from paper_1205_5588_amd._lib import IsfError
+
+    bp = isf.Lattice(_rand_h((16, 128), 3, 4), 3, 1, fmt=1)
+    with pytest.raises(IsfError):
+        bp.run_schedule([(2.0, 0, 3, 0, 0, 40)])
+    h = _rand_h((40, 352), 4, 9)
+    g, o = _pair(isf, h, 4, 77, init=2)
+    with pytest.raises(IsfError):
+        g.run_schedule([(2.0, 0, 3, 0, 0, -1)])  # negative anisotropy field
+    for kernel, tiling in ((2, (16, 16, 4)), (3, (32, 16, 16))):
+        g.set_tuning(tiling[0], tiling[1], tiling[2], True, kernel)
+        with pytest.raises(IsfError):
+            g.schedule_load([(2.0, 0, 3, 0, 0, 40)])
+    g.set_tuning(64, 4, 2, True, 0)
+    g.schedule_load([(2.0, 0, 3, 0, 0, 40)])
+    with pytest.raises(IsfError):
+        g.set_tuning(32, 16, 16, True, 3)  # a whole-sweep kernel under a schedule with the term
+    with pytest.raises(IsfError):
+        isf.Batch(1).advance([g], 3, mode=0)
+    assert g.advance(3) == 3
+    o.run(2.0, 0, 3, 0, 0, 40)
+    _assert_same(g, o)
+    # without the term the whole-sweep kernels are available again
+    g.schedule_load([(2.0, 10, 2, 0)])
+    g.set_tuning(32, 16, 16, True, 3)
+    assert g.advance(2) == 2
+    o.run(2.0, 10, 2)
+    _assert_same(g, o)

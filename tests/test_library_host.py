@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
     from paper_1205_5588_amd import _lib
 
     assert set(syms) == set(_lib.EXPORTS), set(syms) ^ set(_lib.EXPORTS)
-    assert lib.isf_abi_version() == 1
+    assert lib.isf_abi_version() == 2
 
 
 def _bytes(lib, X, Y, Z, fmt=0, reserved=0):
