@@ -27,7 +27,6 @@ bool tiling_supported(const Tiling &tl);
 hipError_t launch_init_i8(const LatDev &L, int32_t mode, hipStream_t s);
 hipError_t launch_phase_i8_list(const LatDev &L, uint32_t ipt, bool small, uint32_t sigma, hipStream_t s);
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s);
-hipError_t launch_aniso_stage(const LatDev &L, hipStream_t s);
 hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 const uint8_t *lists, uint32_t q, hipStream_t s);
 hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
@@ -166,7 +165,7 @@ uint32_t gate_threshold_of(int32_t hs, double T) {
 }
 
 // Thresholds of q + an (words [0, 50)) and q - an (words [50, 100)), q = s (20 n + h),
-// for the anisotropy of Eq. (7); see k_aniso_stage for which half is used when.
+// for the anisotropy of Eq. (7); aniso_select (isf_device.h) picks the halves of a phase.
 void aniso_table_of(double T, int32_t h, int32_t an, uint32_t *out /* kAnWords */) {
     for (int si = 0; si < 2; ++si) {
         const int s = si ? 1 : -1;
@@ -225,8 +224,8 @@ struct isf_lattice {
     // a run of whole-sweep launches is open: the schedule position lives in the
     // parity-buffered positions until k_whole_flush hands it back
     bool whole_active;
-    // the loaded schedule has the anisotropy term: every phase is preceded by
-    // the launch that stages its thresholds
+    // the loaded schedule has the anisotropy term (also in L.aniso, which the
+    // phase kernels read)
     bool aniso;
 };
 
@@ -352,11 +351,6 @@ int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
             continue;
         }
         for (uint32_t s = 0; s < 4; ++s) {
-            if (lat->aniso) {
-                hipError_t e = launch_aniso_stage(lat->L, lat->stream);
-                if (e != hipSuccess)
-                    return fail(ISF_EHIP, "anisotropy launch failed: %s", hipGetErrorString(e));
-            }
             int32_t rc = launch_phase(lat, s);
             if (rc)
                 return rc;
@@ -863,16 +857,20 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
                                hipMemcpyHostToDevice, lat->stream));
         HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, cur_table), tabs.data(),
                                sizeof(uint32_t) * kTableWords, hipMemcpyHostToDevice, lat->stream));
-        if (aniso)
+        if (aniso) {
             HIP_TRY(hipMemcpyAsync(lat->L.atables, atabs.data(), sizeof(uint32_t) * kAnWords * n,
                                    hipMemcpyHostToDevice, lat->stream));
+            HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, cur_atable), atabs.data(),
+                                   sizeof(uint32_t) * kAnWords, hipMemcpyHostToDevice, lat->stream));
+        }
     }
     HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, step), &mid, sizeof mid, hipMemcpyHostToDevice,
                            lat->stream));
     HIP_TRY(hipStreamSynchronize(lat->stream));
     if (aniso != lat->aniso)
-        drop_graph(lat);  // a cached graph holds the staging launches or not
+        drop_graph(lat);  // a cached graph holds the launches' copy of L.aniso
     lat->aniso = aniso;
+    lat->L.aniso = aniso ? 1u : 0u;
     lat->sched_steps = n;
     lat->sched_total = total;
     lat->sched_enqueued = 0;

@@ -127,6 +127,61 @@ __device__ __forceinline__ T aadd(T *p, T v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Anisotropy of Eq. (7) (Section 5), -h_an |M|, with M frozen at the start of
+// each sublattice phase.  The phase's M is the state's M (folded at the end of
+// the previous sweep) plus this sweep's slots (every block of the phases
+// already done has added to them; a kernel boundary orders them).  A flip of
+// spin s changes q by -an (|M - 2s| - |M|) / 2, so each half of the phase's
+// table (s = -1: words 0..24, s = +1: words 25..49) is the step's table of
+// q + an, of q, or of q - an:
+//   M >= 2: s = +1 from q + an, s = -1 from q - an (a field h_an along M);
+//   M <= -2: s = +1 from q - an, s = -1 from q + an;
+//   M = 0: both from q - an (either flip raises |M|);
+//   M = 1: s = +1 from q (|M| falls to 1), s = -1 from q - an;
+//   M = -1: s = +1 from q - an, s = -1 from q.
+// The loads are issued by one whole wave with the block's other loads, and
+// the choice is made when they have landed, so the term adds no memory round
+// trip to a phase.
+static_assert(kSlots == 64, "one slot per lane of the wave that forms M");
+struct AnisoLoads {
+    int64_t dM, M;
+    uint32_t plus, minus;  // word `lane` (< 50) of the tables of q + an and q - an
+};
+
+__device__ __forceinline__ AnisoLoads aniso_issue(const LatDev &L, uint32_t lane) {
+    AnisoLoads a;
+    a.dM = L.slots[lane].dM;
+    a.M = L.st->M;
+    a.plus = lane < 50 ? L.st->cur_atable[lane] : 0u;
+    a.minus = lane < 50 ? L.st->cur_atable[50 + lane] : 0u;
+    return a;
+}
+
+// Word `lane` of the phase's table, from word `base` of the step's plain table.
+// Called by all 64 lanes of the wave that issued the loads.
+__device__ __forceinline__ uint32_t aniso_select(const AnisoLoads &a, uint32_t base, uint32_t lane) {
+    int64_t dM = a.dM;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        dM += __shfl_xor(dM, o, 64);
+    const int64_t M = a.M + dM;
+    if (lane >= 50)
+        return base;  // the gate threshold and padding
+    const bool up = lane >= 25;
+    uint32_t src;  // 0: q, 1: q + an, 2: q - an
+    if (M >= 2)
+        src = up ? 1u : 2u;
+    else if (M <= -2)
+        src = up ? 2u : 1u;
+    else if (M == 0)
+        src = 2u;
+    else if (M == 1)
+        src = up ? 0u : 2u;
+    else
+        src = up ? 2u : 0u;
+    return src == 0u ? base : (src == 1u ? a.plus : a.minus);
+}
+
 // Stage a film's current table and sweep counter into LDS.  Block-wide;
 // ends with a barrier.  Returns false if the film's schedule is finished.
 // kAtomic: the state may have been written earlier in the same launch (the
@@ -233,6 +288,9 @@ __device__ inline void sweep_end(const LatDev &L) {
     next_step = __shfl(next_step, 0, 64);
     if (next_step != 0xFFFFFFFFu && lane < kTableWords)
         sst<kAtomic>(&st->cur_table[lane], sld<kAtomic>(&L.tables[(size_t)next_step * kTableWords + lane]));
+    if (next_step != 0xFFFFFFFFu && L.aniso)
+        for (uint32_t i = lane; i < kAnWords; i += 64)
+            sst<kAtomic>(&st->cur_atable[i], sld<kAtomic>(&L.atables[(size_t)next_step * kAnWords + i]));
 }
 
 // Block reduction of the per-thread partial sums and the slot atomics.  No

@@ -51,6 +51,7 @@ struct alignas(256) DevState {
     int64_t n_bonds;
     int64_t recount[4];     // scratch of the full recount (M, sum s n, sites, occupied pairs)
     uint32_t cur_table[kTableWords];  // thresholds of the current step
+    uint32_t cur_atable[kAnWords];    // its anisotropy thresholds (q + an, q - an), if the schedule has the term
 };
 
 // Per-sweep partial sums, one 128-byte line each so that atomics spread.
@@ -96,7 +97,7 @@ struct LatDev {
     uint32_t key0, key1;
     uint32_t replica;
     uint32_t format;
-    uint32_t pad;
+    uint32_t aniso;       // the loaded schedule has the anisotropy term of Eq. (7)
     // occupied-dword lists (INT8): item = (((z << ybits) | y) << dbits) | d, per sublattice
     const uint32_t *items;
     uint32_t n_items[4];

@@ -72,6 +72,10 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
         tabv = L.st->cur_table[tid];
     if (tid == 0)
         tv = (uint32_t)L.st->t;
+    const bool aniso = L.aniso && tid < 64;  // uniform over each wave
+    AnisoLoads an{};
+    if (aniso)
+        an = aniso_issue(L, tid);
     const uint32_t n = L.n_items[sigma];
     const uint32_t *items = L.items + L.items_off[sigma];
     const uint32_t Y = L.Y, nd = L.nd, rowb = nd * 4u;
@@ -123,6 +127,8 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
         self_off[k] = (size_t)(p1 - base) + oy + db;
         pos[k] = __umul24(__umul24(z, Y) + y, nd) + d;  // Philox counter word 0 = k div 4
     }
+    if (aniso)
+        tabv = aniso_select(an, tabv, tid);
     if (tid < kTableWords)
         tab[tid] = tabv;
     if (tid == 0)
@@ -171,50 +177,6 @@ __global__ __launch_bounds__(64) void k_sweep_end_batch(const BatchEntry *__rest
     const LatDev &L = ents[blockIdx.x].lat;
     if (L.st->step < L.st->n_steps)
         sweep_end<false>(L);
-}
-
-// --------------------------------------------------------------------------
-// Anisotropy of Eq. (7), -h_an |M| (Section 5), with M frozen at the start of
-// each sublattice phase.  Launched (one wave) before every phase of a
-// schedule with the term: it forms the phase's M from the state's M (the end
-// of the previous sweep) and this sweep's slots (the phases already done),
-// and writes the thresholds of the full q into the current table, where the
-// phase kernels read them.  A flip of spin s changes q by
-// -an (|M - 2s| - |M|) / 2, so each half of the table (s = -1, s = +1) is the
-// table of q + an, of q, or of q - an:
-//   M >= 2: s = +1 from q + an, s = -1 from q - an (a field h_an along M);
-//   M <= -2: s = +1 from q - an, s = -1 from q + an;
-//   M = 0: both from q - an (either flip raises |M|);
-//   M = 1: s = +1 from q (|M| falls to 1), s = -1 from q - an;
-//   M = -1: s = +1 from q - an, s = -1 from q.
-// The gate threshold (word kGateWord) is left as it is.
-__global__ __launch_bounds__(64) void k_aniso_stage(LatDev L) {
-    const uint32_t lane = threadIdx.x;
-    int64_t dM = 0;
-    for (uint32_t s = lane; s < kSlots; s += 64)
-        dM += L.slots[s].dM;
-    dM = wave_sum(dM);
-    DevState *st = L.st;
-    const uint32_t step = st->step;
-    if (step >= st->n_steps || lane >= 50)
-        return;
-    const int64_t M = st->M + dM;
-    const bool up = lane >= 25;  // the half of the table for s = +1
-    // 0: q, 1: q + an, 2: q - an
-    uint32_t src;
-    if (M >= 2)
-        src = up ? 1u : 2u;
-    else if (M <= -2)
-        src = up ? 2u : 1u;
-    else if (M == 0)
-        src = 2u;
-    else if (M == 1)
-        src = up ? 0u : 2u;
-    else
-        src = up ? 2u : 0u;
-    const uint32_t v = src == 0u ? L.tables[(size_t)step * kTableWords + lane]
-                                 : L.atables[(size_t)step * kAnWords + (src == 1u ? 0u : 50u) + lane];
-    st->cur_table[lane] = v;
 }
 
 // --------------------------------------------------------------------------
@@ -330,11 +292,6 @@ hipError_t launch_phase_i8_batch(const BatchEntry *ents_dev, uint32_t n_ents, ui
 
 hipError_t launch_sweep_end(const LatDev &L, hipStream_t s) {
     hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(64), 0, s, L);
-    return hipGetLastError();
-}
-
-hipError_t launch_aniso_stage(const LatDev &L, hipStream_t s) {
-    hipLaunchKernelGGL(k_aniso_stage, dim3(1), dim3(64), 0, s, L);
     return hipGetLastError();
 }
 

@@ -112,6 +112,10 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
             runv = L.st->step < L.st->n_steps;
         }
     }
+    const bool aniso = !kAtomic && L.aniso && wid == 0;  // uniform over each wave
+    AnisoLoads an{};
+    if (aniso)
+        an = aniso_issue(L, lane);
 
     const uint32_t py = sigma & 1u, pz = sigma >> 1;
     const uint32_t z = 2 * bz + pz;
@@ -158,6 +162,8 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
         S[r] = sum;
         need[r] = ok && ((~a & 0x01010101u) != 0u);
     }
+    if (aniso)
+        tabv = aniso_select(an, tabv, lane);
     if (tid < kTableWords)
         tab[tid] = tabv;
     if (tid == 0) {
