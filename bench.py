@@ -275,6 +275,26 @@ def cpu_baseline(cfg, h, budget_s=15.0):
                       "C oracle, gcc -O2, OpenMP over rows of one sublattice" % n}
 
 
+def run_only(args, cfg, h):
+    """One extra measurement alone, as in the full run (same workloads and step counts)."""
+    steps = min(args.steps, 40)
+    tl = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    if args.only == "batched":
+        return bench_batched(args)
+    if args.only == "bitpack":
+        if tl is None and not args.no_tune:
+            tb = tune_plain(cfg, h, 1)
+            tl = tuple(tb["tiling"])
+        tuning = None if tl is None else tl + (True, 0)
+        lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 1, steps, 2, tuning)
+        return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
+                "tiling": None if tl is None else list(tl), "ms_per_sweep": round(gpu_ms / sw, 5)}
+    tl = tl or (64, 4, 2)
+    lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 0, steps, 2, tl + (True, 0), an_num=40)
+    return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
+            "an_num": 40, "tiling": list(tl), "ms_per_sweep": round(gpu_ms / sw, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +310,10 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched"], default=None,
+                    help="run only this one of the extra measurements and print its result (for profiling)")
+    ap.add_argument("--tiling", default=None,
+                    help="with --only bitpack or anisotropy: the per-sublattice launch shape tx,ty,rows (no tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -310,6 +334,10 @@ def main():
     t0 = time.perf_counter()
     h = cfg.heights()
     log("height map %.2fs" % (time.perf_counter() - t0))
+
+    if args.only:
+        print(json.dumps({"only": args.only, **run_only(args, cfg, h)}), flush=True)
+        return
 
     from paper_1205_5588_amd.autotune import lookup
 
