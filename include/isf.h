@@ -160,9 +160,12 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
 /* Release the host handle.  Device buffers stay the caller's. */
 int32_t isf_lattice_destroy(isf_lattice *lat);
 
-/* Run a schedule of n_steps steps (each: T, field, sweeps, discarded sweeps)
- * and write one record per step into out[n_steps] (host memory).  Enqueues on
- * the lattice's stream and synchronises before writing out. */
+/* Run a schedule of n_steps steps (each: T, field, sweeps, discarded sweeps,
+ * switching-field gate, anisotropy field; Section 3: a fixed number of MC
+ * steps per temperature or field step) and write one record per step into
+ * out[n_steps] (host memory).  Enqueues on the lattice's stream and
+ * synchronises before writing out.  EINVAL for a step outside the limits of
+ * isf_step (the whole schedule is checked before anything runs). */
 int32_t isf_run_schedule(isf_lattice *lat, const isf_step *steps, uint32_t n_steps, isf_record *out);
 
 /* n_sweeps sweeps at fixed (T, H = h_num/20); sums over the last
@@ -272,7 +275,9 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
  * table on the device.  All lattices of a batch must have the same format
  * and be idle on their own streams; the batch's work runs on the batch
  * stream.  isf_batch_advance advances every lattice by min(max_sweeps, its
- * remaining sweeps) and returns without waiting; isf_batch_sync waits. */
+ * remaining sweeps) and returns without waiting; isf_batch_sync waits.
+ * EINVAL for a lattice whose loaded schedule has the anisotropy term (its
+ * phases need the film's own M, see isf_step.an_num). */
 enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1, ISF_BATCH_WHOLE = 2 };
 
 typedef struct isf_batch isf_batch;
@@ -294,8 +299,9 @@ int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, c
  * as plain launches, with a pair of HIP events around every sublattice
  * launch on the lattice's stream; waits, then writes the mean duration of
  * the launches of sublattice s to ms_per_launch[s] (milliseconds) and the
- * number of sweeps run to *swept.  With ISF_KERNEL_SWEEP the whole-sweep
- * launch is reported in ms_per_launch[0] and the other three entries are 0.
+ * number of sweeps run to *swept.  With ISF_KERNEL_SWEEP or ISF_KERNEL_PIPE
+ * the one launch per sweep is reported in ms_per_launch[0] and the other
+ * three entries are 0.
  * The trajectory is the same as isf_advance. */
 int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms_per_launch[4], uint32_t *swept);
 
