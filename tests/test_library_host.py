@@ -27,6 +27,7 @@ def lib():
 
 def _declared_symbols():
     text = open(os.path.join(ROOT, "include", "isf.h")).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # declarations only, not the comments
     return sorted(set(re.findall(r"\b(isf_[a-z0-9_]+)\s*\(", text)))
 
 
