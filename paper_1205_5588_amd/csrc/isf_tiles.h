@@ -368,19 +368,24 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
         uint32_t F = 0;
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-            if (!((nb.occ >> (4 * g)) & 0xFu))
+            const uint32_t occ4 = (nb.occ >> (4 * g)) & 0xFu;
+            if (!occ4)
                 continue;
             uint32_t u[4];
             philox(g0 + g, t, L.replica, sigma, L.key0, L.key1, u);
+            // the table indices of the group's 4 sites, one byte each: the
+            // group's nibble of each bit plane is spread to bit 0 of 4 bytes
+            // (bit j of a nibble n lands on bit 8j of n * 0x204081; the four
+            // shifted copies of n do not overlap, so nothing carries)
+            uint32_t key = 0;
+#pragma unroll
+            for (int p = 0; p < 6; ++p)
+                key |= ((((ix.b[p] >> (4 * g)) & 0xFu) * 0x00204081u) & 0x01010101u) << p;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int i = 4 * g + j;
-                const uint32_t idx = ((ix.b[0] >> i) & 1u) | (((ix.b[1] >> i) & 1u) << 1) |
-                                     (((ix.b[2] >> i) & 1u) << 2) | (((ix.b[3] >> i) & 1u) << 3) |
-                                     (((ix.b[4] >> i) & 1u) << 4) | (((ix.b[5] >> i) & 1u) << 5);
-                const uint32_t thr = tab[idx];
-                const bool ok = ((nb.occ >> i) & 1u) && (thr == kSentinel || u[j] < thr);
-                F |= (uint32_t)ok << i;
+                const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
+                const bool ok = ((occ4 >> j) & 1u) && (thr == kSentinel || u[j] < thr);
+                F |= (uint32_t)ok << (4 * g + j);
             }
         }
         if (F) {
