@@ -534,6 +534,24 @@ def test_pipe_kernel_large_prefix(isf, tiling):
     _assert_same(g, o)
 
 
+def test_pipe_kernel_large_film_reversal(isf):
+    """The bench's film and launch shape in the reversal regime: all spins up in a reversed
+    field, so most tiles flip more dwords per sweep than their change lists hold and are
+    written whole; then back to a saturating field, where the lists hold them again."""
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=0)
+    g.set_tuning(32, 32, 16, True, 3)
+    _say("pipe kernel, large film reversal")
+    steps = [(c.T, -40, 3, 0), (c.T, -20, 2, 1), (c.T, 120, 3, 0)]
+    rg = g.run_schedule(steps)
+    np.testing.assert_array_equal(rg, np.array([o.run(*st).as_tuple() for st in steps]))
+    _assert_same(g, o)
+    assert rg[0][5] > 0.01 * 3 * o.state()[2]  # heavy flipping in the reversed field
+
+
 def test_pipe_kernel_equals_sweep_kernel_tscan_film(isf):
     """Random start, high temperature on the 512 x 512 x 5 film: pipelined == single-tile whole sweep,
     through graphs of 64 sweeps and timed launches."""
