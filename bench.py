@@ -279,20 +279,23 @@ def run_only(args, cfg, h):
     """One extra measurement alone, as in the full run (same workloads and step counts)."""
     steps = min(args.steps, 40)
     tl = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    kern = 0
+    if tl is not None and len(tl) > 3:
+        tl, kern = tl[:3], tl[3]
     if args.only == "batched":
         return bench_batched(args)
     if args.only == "bitpack":
         if tl is None and not args.no_tune:
             tb = tune_plain(cfg, h, 1)
             tl = tuple(tb["tiling"])
-        tuning = None if tl is None else tl + (True, 0)
+        tuning = None if tl is None else tl + (True, 0)  # bit-packed films have no list kernel
         lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 1, steps, 2, tuning)
         return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
                 "tiling": None if tl is None else list(tl), "ms_per_sweep": round(gpu_ms / sw, 5)}
     tl = tl or (64, 4, 2)
-    lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 0, steps, 2, tl + (True, 0), an_num=40)
+    lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 0, steps, 2, tl + (True, kern), an_num=40)
     return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
-            "an_num": 40, "tiling": list(tl), "ms_per_sweep": round(gpu_ms / sw, 5)}
+            "an_num": 40, "tiling": list(tl), "kernel": kern, "ms_per_sweep": round(gpu_ms / sw, 5)}
 
 
 def main():
@@ -313,7 +316,8 @@ def main():
     ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched"], default=None,
                     help="run only this one of the extra measurements and print its result (for profiling)")
     ap.add_argument("--tiling", default=None,
-                    help="with --only bitpack or anisotropy: the per-sublattice launch shape tx,ty,rows (no tuning)")
+                    help="with --only bitpack or anisotropy: the per-sublattice launch shape tx,ty,rows[,kernel] "
+                         "(kernel 0: tiles, 1: occupied-dword lists; no tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
