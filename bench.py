@@ -275,6 +275,22 @@ def cpu_baseline(cfg, h, budget_s=15.0):
                       "C oracle, gcc -O2, OpenMP over rows of one sublattice" % n}
 
 
+def copy_calibration(args):
+    """Three plain device copies of --copy-mib MiB: what rocprofv3's byte counters read for
+    them scales the counters of the kernels profiled in the same command."""
+    if not args.copy_mib:
+        return
+    import torch
+
+    n = args.copy_mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x %d bytes" % n)
+
+
 def run_only(args, cfg, h):
     """One extra measurement alone, as in the full run (same workloads and step counts)."""
     steps = min(args.steps, 40)
@@ -340,7 +356,9 @@ def main():
     log("height map %.2fs" % (time.perf_counter() - t0))
 
     if args.only:
-        print(json.dumps({"only": args.only, **run_only(args, cfg, h)}), flush=True)
+        res = run_only(args, cfg, h)
+        copy_calibration(args)
+        print(json.dumps({"only": args.only, **res}), flush=True)
         return
 
     from paper_1205_5588_amd.autotune import lookup
@@ -405,14 +423,7 @@ def main():
         cpu_base = cpu_baseline(cfg, h)
         log("cpu baseline:", cpu_base)
 
-    if args.copy_mib:
-        n = args.copy_mib << 20
-        src = torch.ones(n, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 x %d bytes" % n)
+    copy_calibration(args)
 
     Nc = cfg.X * cfg.Y * cfg.Z // 2
     line = {
