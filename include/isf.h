@@ -26,7 +26,11 @@
  *     sublattice are updated at once); the sweep counter t counts sweeps
  *     from 0 over the life of the lattice;
  *   - a temperature or field step is a fixed number of sweeps (Section 3:
- *     each step of temperature or field gets a finite number of MC steps).
+ *     each step of temperature or field gets a finite number of MC steps);
+ *   - optional per step: the switching-field gate of Eq. 9 (steps 4-5 of
+ *     Section 5; a site may flip only if its own gate draw passes, see
+ *     isf_step.hs_num) and the anisotropy term -h_an |M| of Eq. 7 (with M
+ *     frozen at the start of each sublattice phase, see isf_step.an_num).
  *
  * Every trajectory is therefore integer and reproducible bit for bit: it does
  * not depend on the storage format, tiling, batch position or device.
