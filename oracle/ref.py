@@ -10,7 +10,9 @@ Contents:
   gate_threshold     -- Eq. (9) switching-field gate floor(2^32 exp(-|h_s|/T)), h_s = hs_num/20
   anisotropy_q       -- the change of the anisotropy energy -h_an |M| of Eq. (7)
                         for one flip, in tenths
-  TinyFilm           -- the sweep of Section 5 (steps 1-3) on a site list
+  TinyFilm           -- the sweep of Section 5 (steps 1-3) on a site list, and a
+                        run of sweeps at one (T, H) whose first sweeps are
+                        discarded from the recorded sums
   enumerate_exact    -- partition function of Eq. (4) and Gibbs averages of
                         Eq. (5) by enumerating all 2^N configurations
   phase_matrix, sweep_matrix -- the Markov chain of Eq. (6) written as
@@ -173,6 +175,27 @@ class TinyFilm:
                     acc += 1
         self.t += 1
         return acc
+
+    def run(self, T: float, h_num: int, n_sweeps: int, n_discard: int = 0, hs_num: int = 0,
+            an_num: int = 0) -> Tuple[int, int, int, int, int, int]:
+        """n_sweeps sweeps at one (T, H); the first n_discard of them are equilibration
+        (the fixed number of Monte Carlo steps per temperature or field step of
+        Section 3, of which the M(T) curve of Fig. 3 keeps the later ones).  Returns
+        (M, E_bond) after the last sweep and, over the kept sweeps only, the sums of M,
+        |M| and E_bond taken after each sweep and the number of accepted flips."""
+        if not 0 <= n_discard <= n_sweeps:
+            raise ValueError("n_discard must lie in [0, n_sweeps]")
+        kept_M = kept_absM = kept_E = kept_acc = 0
+        for i in range(n_sweeps):
+            acc = self.sweep(T, h_num, hs_num, an_num)
+            if i < n_discard:
+                continue
+            m = self.magnetisation()
+            kept_M += m
+            kept_absM += abs(m)
+            kept_E += self.bond_energy()
+            kept_acc += acc
+        return (self.magnetisation(), self.bond_energy(), kept_M, kept_absM, kept_E, kept_acc)
 
 
 def enumerate_exact(film: TinyFilm, T: float, h_num: int, an_num: int = 0):

@@ -752,3 +752,80 @@ def test_anisotropy_supports_the_spin_excess_at_low_temperature(oracle_lib):
     assert r.M == N and r.accepted == 0
     r = f.run(1e-3, -10, 1, 0, 0, 0)
     assert r.M == -N and r.accepted == N
+
+
+# --------------------------------------------------------------------------- discarded sweeps
+# A run of n sweeps at one (T, H) keeps the sums of M, |M|, E_bond and the accepted
+# flips over its last n - d sweeps only: the first d are equilibration (Section 3:
+# a fixed number of Monte Carlo steps per temperature or field step; the M(T)
+# curve of Fig. 3 averages after it).  The pins below fix that window by its
+# definition: one-sweep runs (d = 0, whose M and E_bond are the recount's) summed
+# by hand over i >= d, a second implementation, and the split of a run at d.
+WINDOWS = [(12, 0), (12, 1), (12, 5), (12, 11), (12, 12), (1, 0), (1, 1), (40, 8)]
+
+
+@pytest.mark.parametrize("n,d", WINDOWS)
+def test_discard_window_is_the_sum_over_the_later_sweeps(oracle_lib, n, d):
+    rng = np.random.default_rng(31 + n + 100 * d)
+    Y, X, Z = 24, 40, 4
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    T, hn = 3.5, 7   # hot enough that M, E_bond and the accepted count change every sweep
+    a = cpu.Film(h, Z, 0xABCDEF, 3, init=cpu.INIT_RANDOM)
+    b = cpu.Film(h, Z, 0xABCDEF, 3, init=cpu.INIT_RANDOM)
+    a.run(T, hn, 3)   # the window is relative to the call, not to the chain's start
+    b.run(T, hn, 3)
+    rec = a.run(T, hn, n, d).as_tuple()
+    per = []
+    for _ in range(n):
+        r = b.run(T, hn, 1, 0)
+        assert (r.M, r.E) == b.recount()
+        assert (r.sum_M, r.sum_absM, r.sum_E) == (r.M, abs(r.M), r.E)
+        per.append(r)
+    kept = per[d:]
+    want = (per[-1].M, per[-1].E, sum(r.M for r in kept), sum(abs(r.M) for r in kept), sum(r.E for r in kept),
+            sum(r.accepted for r in kept))
+    assert rec == want
+    assert len({r.accepted for r in per}) > 1 or n == 1
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    assert a.state() == b.state()
+
+
+@pytest.mark.parametrize("n,d", [(6, 0), (6, 2), (6, 6), (5, 4)])
+def test_discard_window_c_matches_python(oracle_lib, n, d):
+    rng = np.random.default_rng(77 + d)
+    Y, X, Z = 6, 10, 3
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    key, rep = 0x1234_5678_9ABC, 5
+    tf = ref.TinyFilm(h, Z, seed=key, replica=rep)
+    tf.init_random()
+    cf = cpu.Film(h, Z, key, rep, init=cpu.INIT_RANDOM)
+    for T, hn, hs, an in ((2.0, 11, 0, 0), (5.0, -3, 40, 0), (1.5, 0, 0, 20)):
+        rp = tf.run(T, hn, n, d, hs, an)
+        rc = cf.run(T, hn, n, d, hs, an).as_tuple()
+        assert rp == rc, (T, hn, hs, an)
+    sp = cf.spins()
+    assert all(sp[z, y, x] == tf.s[i] for i, (x, y, z) in enumerate(tf.sites))
+
+
+def test_discard_window_splits_the_run(oracle_lib):
+    """run(n, d) == run(d, d) followed by run(n - d, 0): the discarded sweeps advance
+    the chain and contribute nothing; the kept ones are the whole second run.  Also
+    the temperature-scan shape (discard per temperature, chain continued across)."""
+    from isf_workloads import config_plain_tscan
+
+    c = config_plain_tscan()
+    rng = np.random.default_rng(5)
+    Y, X, Z = 32, 32, c.Z
+    h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+    a = cpu.Film(h, Z, c.mc_seed, init=cpu.INIT_RANDOM)
+    b = cpu.Film(h, Z, c.mc_seed, init=cpu.INIT_RANDOM)
+    n, d = 25, 5
+    temps = c.temps[::11]
+    got = cpu.tscan(a, temps, n, d)
+    for i, T in enumerate(temps):
+        head = b.run(T, 0, d, d).as_tuple()
+        assert head[2:] == (0, 0, 0, 0)
+        tail = b.run(T, 0, n - d, 0).as_tuple()
+        assert tuple(got[i]) == tail, T
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    assert a.state() == b.state()
