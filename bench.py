@@ -4,13 +4,17 @@ The measured workload is the large plain hysteresis film (2048 x 2048 x 8
 FCC film, sigma = 16 px height map, T = 4.0, field ramp +6 -> -6 -> +6 in
 steps of 0.05, 50 sweeps per field step, int8 spins, all +1 at start).  One
 bench "step" is one field step: 50 sweeps over the whole film (all four
-sublattices, with the per-sweep observables and the step record).  Inputs are
-resident in HBM before the timed region starts.
+sublattices, with the per-sweep observables and the step record).  Every
+run sweeps the whole 481-step loop; the --steps timed steps are spread
+evenly over it (both saturated ends, both field reversals), each bracketed
+by HIP events on the film's stream, and the whole loop's rate is reported
+beside them.  Inputs are resident in HBM before the timed region starts.
 
 Beside the plain path the JSON line carries the same film in the bit-packed
-format, the batched workload (256 replicas of uneven films) and the serving
-loop (p50/p99 latency), all on the same GPU, plus the roofline of the
-dominant kernel and the CPU oracle timed on a bounded sample.
+format, the gated and anisotropic ramps, the batched workload (256 replicas
+of uneven films) and the serving loop (p50/p99 latency), all on the same
+GPU, plus the roofline of the dominant kernel, a draw-only ALU ceiling and
+the CPU oracle timed on a bounded sample.
 """
 
 from __future__ import annotations
@@ -33,12 +37,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def plain_steps(cfg, first, count, hs_num=0, an_num=0):
-    hn = cfg.h_nums
-    return [(cfg.T, hn[(first + i) % len(hn)], cfg.sweeps_per_step, 0, hs_num, an_num) for i in range(count)]
+def spread_steps(n_total, k):
+    """k distinct field steps spread evenly over a ramp of n_total steps, both ends included."""
+    if k >= n_total:
+        return list(range(n_total))
+    if k <= 1:
+        return [n_total // 2]
+    return sorted({int(i * (n_total - 1) / (k - 1) + 0.5) for i in range(k)})
 
 
-def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0, an_num=0):
+def ramp_schedule(cfg, hs_num=0, an_num=0):
+    return [(cfg.T, hv, cfg.sweeps_per_step, 0, hs_num, an_num) for hv in cfg.h_nums]
+
+
+def bench_ramp(cfg, h, fmt, k, warmup, tuning=None, hs_num=0, an_num=0):
+    """The whole ramp on a fresh film, with k of its field steps timed.
+
+    `warmup` untimed steps at the ramp's first field come first.  Then the
+    ramp's 481 steps are enqueued as one schedule in chunks; HIP events on the
+    film's stream bracket each of the k timed steps (spread over the loop) and
+    the whole ramp.  Returns the lattice and the measurements."""
     import torch
 
     from paper_1205_5588_amd.lattice import Lattice
@@ -49,54 +67,113 @@ def bench_plain(cfg, h, fmt, steps, warmup, tuning=None, hs_num=0, an_num=0):
             lat.attach_items()
         lat.set_tuning(*tuning)
     n_occ = lat.observables()["n_occ"]
+    sched = ramp_schedule(cfg, hs_num, an_num)
+    sps = cfg.sweeps_per_step
     if warmup:
-        lat.run_schedule(plain_steps(cfg, 0, warmup, hs_num, an_num))
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+        lat.run_schedule([sched[0]] * warmup)
+    sel = spread_steps(len(sched), k)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sel]
+    whole0, whole1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat.schedule_load(sched)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(lat.stream)
-    recs = lat.run_schedule(plain_steps(cfg, warmup, steps, hs_num, an_num))
-    ev1.record(lat.stream)
+    whole0.record(lat.stream)
+    pos = 0
+    for s, (a, b) in zip(sel, ev):
+        if s > pos:
+            lat.advance((s - pos) * sps)
+        a.record(lat.stream)
+        lat.advance(sps)
+        b.record(lat.stream)
+        pos = s + 1
+    if pos < len(sched):
+        lat.advance((len(sched) - pos) * sps)
+    whole1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    sweeps = steps * cfg.sweeps_per_step
-    return lat, n_occ, sweeps, wall, gpu_ms, recs
+    recs = lat.records()
+    timed_ms = sum(a.elapsed_time(b) for a, b in ev)
+    whole_ms = whole0.elapsed_time(whole1)
+    sweeps = len(sel) * sps
+    return {"lat": lat, "n_occ": n_occ, "steps": sel, "sweeps": sweeps, "timed_ms": timed_ms,
+            "value": n_occ * sweeps / (timed_ms * 1e-3), "whole_ms": whole_ms, "wall_s": wall,
+            "whole_value": n_occ * len(sched) * sps / (whole_ms * 1e-3), "records": recs}
 
 
-def roofline_int8(lat, cfg, region_ms_per_sweep, n_sweeps=40):
-    """Mean duration of the dominant kernel and its algorithmic bandwidth.
+def launch_durations(lat, cfg, steps, hs_num=0, an_num=0):
+    """Mean duration of each launch of the film's sweep kernel over the given field
+    steps of a second pass of the ramp: a pair of timing-only HIP events around every
+    launch (isf_time_launches), untimed graph replay elsewhere.  Returns the mean
+    milliseconds per launch of each of the four sublattices (whole-sweep kernels:
+    entry 0 is the sweep)."""
+    sched = ramp_schedule(cfg, hs_num, an_num)
+    sps = cfg.sweeps_per_step
+    lat.schedule_load(sched)
+    tot = [0.0, 0.0, 0.0, 0.0]
+    n = 0
+    pos = 0
+    for s in steps:
+        if s > pos:
+            lat.advance((s - pos) * sps)
+        ms, got = lat.time_launches(sps)
+        tot = [t + m * got for t, m in zip(tot, ms)]
+        n += got
+        pos = s + 1
+    if pos < len(sched):
+        lat.advance((len(sched) - pos) * sps)
+    lat.records()
+    return [t / max(n, 1) for t in tot]
 
-    A whole-sweep schedule launches exactly one kernel per sweep, so its mean
-    launch duration is the timed region's time per sweep (HIP events on the
-    film's stream around the whole timed schedule, gaps between launches
-    included); HIP event pairs around every launch are reported beside it
-    (ms_per_launch_events).  For the sublattice kernels, four launches and the
-    sweep end share a sweep, and the event pairs around each launch are used.
+
+def roofline_int8(lat, cfg, steps, region_ms_per_sweep):
+    """Algorithmic bandwidth of the dominant kernel against the 8 TB/s HBM peak.
 
     Algorithmic bytes follow the four-phase schedule (N_c = X Y Z / 2 stored
-    sites): a sweep reads every stored byte and writes its active quarter in each
-    of its four sublattice phases, 5 N_c bytes per sweep; a sublattice launch is
-    one phase (1.25 N_c), a whole-sweep launch is one sweep (5 N_c).  The
-    schedule-free lower bound, every byte read and written once per sweep
-    (2 N_c), is reported beside it as frac_min_bytes."""
-    lat.schedule_load([(cfg.T, cfg.h_nums[0], n_sweeps, 0)])
-    ms, n = lat.time_launches(n_sweeps)
+    sites): each sublattice phase reads every stored byte and writes its active
+    quarter, 1.25 N_c per phase and 5 N_c per sweep.  A whole-sweep launch is one
+    sweep (5 N_c), a sublattice launch one phase (1.25 N_c).  The launch duration
+    is the mean over the timed field steps of a second pass of the ramp, from
+    timing-only HIP events around every launch; the timed region's time per
+    sweep, launch gaps included, is reported beside it.  The film (16 MiB) sits in
+    the 256 MB Infinity Cache and the whole-sweep kernels move about a third of
+    the four-phase bytes (traffic), so the fraction is the schedule's figure of
+    merit, not a measure of DRAM use: the kernel is bound by its integer VALU and
+    LDS work and their latency (profiles/)."""
+    ms = launch_durations(lat, cfg, steps)
     Nc = cfg.X * cfg.Y * cfg.Z // 2
     if lat.get_tuning()[4] in (KERNEL_SWEEP, KERNEL_PIPE):
-        mean_ms, bytes_per_launch, min_bytes = region_ms_per_sweep, 5.0 * Nc, 2.0 * Nc
-        ms = ms[:1]
+        mean_ms, bytes_per_launch, min_bytes = ms[0], 5.0 * Nc, 2.0 * Nc
     else:
         mean_ms, bytes_per_launch, min_bytes = sum(ms) / 4.0, 1.25 * Nc, 0.5 * Nc
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
-    traffic = measured_traffic(lat_kernel_name(lat))
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": lat_kernel_name(lat), "ms_per_launch": round(mean_ms, 5),
-            "ms_per_launch_events": [round(v, 5) for v in ms],
-            "bytes_per_launch": int(bytes_per_launch),
-            "frac_min_bytes": round(min_bytes / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    kernel = lat_kernel_name(lat)
+    traffic = measured_traffic(kernel)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": kernel, "ms_per_launch": round(mean_ms, 5),
+           "ms_per_launch_by_sublattice": [round(v, 5) for v in ms],
+           "ms_per_sweep_region": round(region_ms_per_sweep, 5),
+           "bytes_per_launch": int(bytes_per_launch), "bytes_model": "four-phase schedule, 5 N_c per sweep",
+           "frac_min_bytes": round(min_bytes / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "launches_timed": len(steps) * cfg.sweeps_per_step,
+           "limiter": "integer VALU + LDS latency; film resident in the Infinity Cache"}
+    if traffic:
+        out["traffic_frac"] = round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def alu_ceiling(lat, cfg, n_sweeps=200):
+    """Draw-only ceiling: the same film's stored dwords draw their attempts' Philox
+    numbers (one 4x32-10 call per dword and sweep, vacant dwords included) and
+    nothing else; attempts/s if a sweep cost only its draws."""
+    lat.draw_xor(0, 4)
+    _, ms = lat.draw_xor(1000, n_sweeps)
+    n_occ = lat.observables()["n_occ"]
+    Nc = cfg.X * cfg.Y * cfg.Z // 2
+    return {"kind": "Philox4x32-10 draws only, one call per stored dword and sweep", "sweeps": n_sweeps,
+            "us_per_sweep": round(ms * 1e3 / n_sweeps, 3),
+            "draws_per_s": round(Nc * n_sweeps / (ms * 1e-3), 1),
+            "attempts_per_s": round(n_occ * n_sweeps / (ms * 1e-3), 1)}
 
 
 KERNEL_SOURCES = ("isf_sweep.hip", "isf_device.h", "isf_internal.h")
@@ -213,16 +290,17 @@ def bench_batched(args):
 
 
 def serving_inputs(args):
-    """Requests and their height maps, generated before the GPU is touched (the
-    height maps are the requests' payload, not server work)."""
-    import multiprocessing as mp
+    """Requests and their height maps (the requests' payload, not server work),
+    built in this process with a pool of threads (numpy's FFTs release the GIL)
+    only when the serving measurement runs."""
+    import concurrent.futures as cf
 
-    from isf_workloads import serving_requests
+    from isf_workloads import height_map, serving_requests
 
     reqs = serving_requests(duration=args.serve_duration)
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        heights = pool.map(_heights_of, [(q.X, q.Y, q.Z, q.sigma, q.seed) for q in reqs], chunksize=8)
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        heights = list(ex.map(lambda q: height_map(q.X, q.Y, q.Z, q.sigma, q.seed), reqs))
     log("serving: %d requests, height maps %.1fs" % (len(reqs), time.perf_counter() - t0))
     return reqs, {q.rid: hh for q, hh in zip(reqs, heights)}
 
@@ -246,13 +324,6 @@ def bench_serving(args, reqs, hmap):
     s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep"}[args.serve_mode]
     s["arrivals"] = "Poisson 50 req/s for %g s" % args.serve_duration
     return s
-
-
-def _heights_of(a):
-    from isf_workloads import height_map
-
-    X, Y, Z, sig, seed = a
-    return height_map(X, Y, Z, sig, seed)
 
 
 def cpu_baseline(cfg, h, budget_s=15.0):
@@ -291,9 +362,29 @@ def copy_calibration(args):
     log("copy calibration: 3 x %d bytes" % n)
 
 
+def ramp_summary(r, cfg):
+    """The JSON fields of one ramp measurement (bench_ramp)."""
+    sps = cfg.sweeps_per_step
+    return {"value": round(r["value"], 1), "unit": "spin-flip attempts/s", "steps_timed": len(r["steps"]),
+            "ms_per_sweep": round(r["timed_ms"] / r["sweeps"], 5),
+            "whole_ramp": {"steps": len(cfg.h_nums), "attempts_per_s": round(r["whole_value"], 1),
+                           "ms_per_sweep": round(r["whole_ms"] / (len(cfg.h_nums) * sps), 5)}}
+
+
+def bitpack_fields(r, cfg):
+    """Bit-packed film: its rate and its fraction of HBM at the four-phase schedule's
+    bytes for 1-bit spins and occupancy, 1.125 N_c per sweep."""
+    out = ramp_summary(r, cfg)
+    Nc = cfg.X * cfg.Y * cfg.Z // 2
+    gbs = 1.125 * Nc / (out["ms_per_sweep"] * 1e-3) / 1e9
+    out["hbm"] = {"bytes_per_sweep": int(1.125 * Nc), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["tuning"] = list(r["lat"].get_tuning())
+    return out
+
+
 def run_only(args, cfg, h):
     """One extra measurement alone, as in the full run (same workloads and step counts)."""
-    steps = min(args.steps, 40)
     tl = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
     kern = 0
     if tl is not None and len(tl) > 3:
@@ -304,20 +395,19 @@ def run_only(args, cfg, h):
         if tl is None and not args.no_tune:
             tb = tune_plain(cfg, h, 1)
             tl = tuple(tb["tiling"])
-        tuning = None if tl is None else tl + (True, 0)  # bit-packed films have no list kernel
-        lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 1, steps, 2, tuning)
-        return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
-                "tiling": None if tl is None else list(tl), "ms_per_sweep": round(gpu_ms / sw, 5)}
+            kern = tb["kernel"]
+        tuning = None if tl is None else tl + (True, kern)
+        return bitpack_fields(bench_ramp(cfg, h, 1, args.steps, 2, tuning), cfg)
     tl = tl or (64, 4, 2)
-    lat, n_occ, sw, wall, gpu_ms, recs = bench_plain(cfg, h, 0, steps, 2, tl + (True, kern), an_num=40)
-    return {"value": round(n_occ * sw / (gpu_ms * 1e-3), 1), "unit": "spin-flip attempts/s", "steps": steps,
-            "an_num": 40, "tiling": list(tl), "kernel": kern, "ms_per_sweep": round(gpu_ms / sw, 5)}
+    r = bench_ramp(cfg, h, 0, args.steps, 2, tl + (True, kern), an_num=40)
+    return {**ramp_summary(r, cfg), "an_num": 40, "tiling": list(tl), "kernel": kern}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=481)
+    ap.add_argument("--steps", type=int, default=481,
+                    help="field steps timed, spread evenly over the 481-step loop (the whole loop always runs)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
@@ -332,7 +422,7 @@ def main():
     ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched"], default=None,
                     help="run only this one of the extra measurements and print its result (for profiling)")
     ap.add_argument("--tiling", default=None,
-                    help="with --only bitpack or anisotropy: the per-sublattice launch shape tx,ty,rows[,kernel] "
+                    help="with --only bitpack or anisotropy: the launch shape tx,ty,rows[,kernel] "
                          "(kernel 0: tiles, 1: occupied-dword lists; no tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -340,10 +430,9 @@ def main():
               "(replicas and requests shard across GPUs without communication; see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-
-    serve_in = None
-    if not args.no_extra and not args.no_serve:
-        serve_in = serving_inputs(args)   # CPU only, before the GPU is initialised
+    if args.steps < 1:
+        print("bench.py: --steps must be at least 1", file=sys.stderr)
+        sys.exit(2)
 
     import torch
 
@@ -370,52 +459,51 @@ def main():
         tune_info = tune_plain(cfg, h, 0)
         tuning = tuple(tune_info["tiling"]) + (tune_info["use_graph"], tune_info["kernel"])
         log("plain tuning %.1fs: %s" % (time.perf_counter() - t0, tune_info))
-    lat, n_occ, sweeps, wall, gpu_ms, recs = bench_plain(cfg, h, 0, args.steps, args.warmup, tuning)
-    value = n_occ * sweeps / (gpu_ms * 1e-3)
-    log("plain int8: %d steps, %d sweeps, %.3f s wall, %.3f ms gpu, %.3e attempts/s" %
-        (args.steps, sweeps, wall, gpu_ms, value))
+    r = bench_ramp(cfg, h, 0, args.steps, args.warmup, tuning)
+    lat, n_occ, sweeps = r["lat"], r["n_occ"], r["sweeps"]
+    log("plain int8: %d timed steps of %d, %d sweeps, %.3f ms timed, %.3e attempts/s; whole loop %.3f ms, "
+        "%.3e attempts/s" % (len(r["steps"]), len(cfg.h_nums), sweeps, r["timed_ms"], r["value"], r["whole_ms"],
+                            r["whole_value"]))
     lat_stats = lat.film_stats()
-    roof = roofline_int8(lat, cfg, gpu_ms / sweeps)
+    roof = roofline_int8(lat, cfg, r["steps"], r["timed_ms"] / sweeps)
     log("roofline:", roof)
+    ceiling = alu_ceiling(lat, cfg)
+    log("draw-only ceiling:", ceiling)
     pmoke = bench_surface_image(lat, cfg)
     log("pmoke image:", pmoke)
     del lat
 
-    extra = {"pmoke_image": pmoke, "film": lat_stats, "tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
+    extra = {"whole_ramp": ramp_summary(r, cfg)["whole_ramp"], "alu_ceiling": ceiling, "pmoke_image": pmoke,
+             "film": lat_stats,
+             "tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
                         "tuned": tune_info is not None,
                         "candidates": 0 if tune_info is None else len(tune_info["all"])}}
     if not args.no_extra:
         tb = None if args.no_tune else tune_plain(cfg, h, 1)
-        tbt = None if tb is None else tuple(tb["tiling"]) + (tb["use_graph"], tb["kernel"])
-        lat_b, n_occ_b, sw_b, wall_b, gpu_ms_b, recs_b = bench_plain(cfg, h, 1, min(args.steps, 40), 2, tbt)
-        extra["bitpack"] = {"value": round(n_occ_b * sw_b / (gpu_ms_b * 1e-3), 1),
-                            "unit": "spin-flip attempts/s", "steps": min(args.steps, 40),
-                            "tiling": None if tb is None else tb["tiling"]}
+        tbt = lookup(cfg.X, cfg.Y, cfg.Z, 1) if tb is None else tuple(tb["tiling"]) + (tb["use_graph"], tb["kernel"])
+        rb = bench_ramp(cfg, h, 1, args.steps, 2, tbt)
+        extra["bitpack"] = bitpack_fields(rb, cfg)
         log("bitpack:", extra["bitpack"])
-        del lat_b
+        del rb
         # the same ramp behind the switching-field gate of Eq. 9 with h_s = 2 (hs_num = 40)
-        lat_g, n_occ_g, sw_g, wall_g, gpu_ms_g, recs_g = bench_plain(cfg, h, 0, min(args.steps, 40), 2, tuning,
-                                                                     hs_num=40)
-        extra["gated"] = {"value": round(n_occ_g * sw_g / (gpu_ms_g * 1e-3), 1), "unit": "spin-flip attempts/s",
-                          "steps": min(args.steps, 40), "hs_num": 40,
-                          "accepted_per_attempt": round(float(recs_g[:, 5].sum()) / (n_occ_g * sw_g), 5)}
+        rg = bench_ramp(cfg, h, 0, args.steps, 2, tuning, hs_num=40)
+        extra["gated"] = {**ramp_summary(rg, cfg), "hs_num": 40,
+                          "accepted_per_attempt": round(float(rg["records"][:, 5].sum()) /
+                                                        (rg["n_occ"] * len(cfg.h_nums) * cfg.sweeps_per_step), 5)}
         log("gated:", extra["gated"])
-        del lat_g
+        del rg
         # the same ramp with the anisotropy term of Eq. 7, h_an = 2 (an_num = 40), on the
         # per-sublattice kernels (M frozen per phase)
         an_tl = (64, 4, 2, True, 0)
-        lat_a, n_occ_a, sw_a, wall_a, gpu_ms_a, recs_a = bench_plain(cfg, h, 0, min(args.steps, 40), 2, an_tl,
-                                                                     an_num=40)
-        extra["anisotropy"] = {"value": round(n_occ_a * sw_a / (gpu_ms_a * 1e-3), 1),
-                               "unit": "spin-flip attempts/s", "steps": min(args.steps, 40), "an_num": 40,
-                               "tiling": list(an_tl[:3]), "kernel": "k_phase_i8",
-                               "ms_per_sweep": round(gpu_ms_a / sw_a, 5)}
+        ra = bench_ramp(cfg, h, 0, args.steps, 2, an_tl, an_num=40)
+        extra["anisotropy"] = {**ramp_summary(ra, cfg), "an_num": 40, "tiling": list(an_tl[:3]),
+                               "kernel": "k_phase_i8"}
         log("anisotropy:", extra["anisotropy"])
-        del lat_a
+        del ra
         extra["batched"] = bench_batched(args)
         log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
         if not args.no_serve:
-            extra["serving"] = bench_serving(args, *serve_in)
+            extra["serving"] = bench_serving(args, *serving_inputs(args))
             log("serving:", extra["serving"])
 
     cpu_base = None
@@ -428,12 +516,12 @@ def main():
     Nc = cfg.X * cfg.Y * cfg.Z // 2
     line = {
         "metric": "spin-flip attempts/s",
-        "value": round(value, 1),
+        "value": round(r["value"], 1),
         "unit": "spin-flip attempts/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": len(r["steps"]),
         "warmup": args.warmup,
-        "ms_per_step": round(gpu_ms / args.steps, 4),
+        "ms_per_step": round(r["timed_ms"] / len(r["steps"]), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -442,7 +530,9 @@ def main():
         "config": {"workload": "plain hysteresis 2048x2048x8 FCC film, sigma=16 px, T=4.0, H +6->-6->+6 step 0.05, "
                                "50 sweeps per field step, int8 spins, 1 replica",
                    "n_occ": n_occ, "stored_sites": Nc, "sweeps_per_step": cfg.sweeps_per_step,
-                   "effective_GBps_4pass": round(5 * Nc * sweeps / (gpu_ms * 1e-3) / 1e9, 1)},
+                   "timed_steps": "%d of the loop's %d field steps, spread evenly over it (both reversals "
+                                  "included); the whole loop runs" % (len(r["steps"]), len(cfg.h_nums)),
+                   "effective_GBps_4pass": round(5 * Nc * sweeps / (r["timed_ms"] * 1e-3) / 1e9, 1)},
         "roofline": roof,
         "cpu_baseline": cpu_base,
     }

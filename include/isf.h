@@ -309,6 +309,18 @@ int32_t isf_batch_run(isf_batch *b, isf_lattice *const *lats, uint32_t n_lats, c
  * The trajectory is the same as isf_advance. */
 int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms_per_launch[4], uint32_t *swept);
 
+/* Measurement and generator check: the draw-only ceiling of a sweep.  For
+ * n_sweeps sweeps t = t0, t0 + 1, ... (the Philox counter's word 1 is t mod
+ * 2^32) every stored dword of the film -- vacancies included -- draws the
+ * four numbers of its attempt (Section 5's uniform random number, Philox
+ * counter (dword index, t, replica, sublattice), key = the film's seed), and
+ * nothing else is done.  The XOR of all words drawn is written to *xor_dev, a
+ * 4-byte device buffer owned by the caller; the film's spins and state are
+ * not touched.  *ms (may be null) receives the launch time in milliseconds
+ * from a pair of HIP events on the lattice's stream.  Synchronous.
+ * Errors: ISF_EINVAL for a null xor_dev or n_sweeps = 0. */
+int32_t isf_draw_xor(isf_lattice *lat, uint32_t t0, uint32_t n_sweeps, uint32_t *xor_dev, float *ms);
+
 /* Full recount of M and E_bond from the spins on the device (not the tracked
  * values); used to check the incremental bookkeeping.  Synchronous. */
 int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E_bond);

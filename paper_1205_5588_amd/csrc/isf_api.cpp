@@ -31,6 +31,8 @@ hipError_t launch_sweep_i8_halo(const LatDev &L, const Tiling &tl, const uint8_t
                                 const uint8_t *lists, uint32_t q, hipStream_t s);
 hipError_t launch_whole_prime(const LatDev &L, uint32_t q, hipStream_t s);
 hipError_t launch_surface_image(const LatDev &L, const uint8_t *spins, int8_t *img, hipStream_t s);
+hipError_t launch_draw_xor(const LatDev &L, uint32_t t0, uint32_t n_sweeps, uint32_t *out, uint32_t n_cu,
+                           hipStream_t s);
 hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *begins, uint32_t n_ents,
                                       uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s);
 uint32_t halo_tiles(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t &nbx);
@@ -204,10 +206,14 @@ struct isf_lattice {
     uint32_t sched_steps;
     uint64_t sched_total;      // sweeps in the loaded schedule
     uint64_t sched_enqueued;   // sweeps enqueued so far
-    // cached graph of graph_sweeps sweeps
+    // cached graph of graph_sweeps sweeps, and one of the last shorter count
+    // asked for (a request's remainder, e.g. one field step)
     hipGraphExec_t graph;
     uint32_t graph_sweeps;
     Tiling graph_tiling;
+    hipGraphExec_t tail_graph;
+    uint32_t tail_sweeps;
+    Tiling tail_tiling;
     // occupied-dword lists attached (INT8)
     bool items_attached;
     // second copy of the spins for the whole-sweep kernel (INT8), at the end of
@@ -363,19 +369,31 @@ int32_t enqueue_sweeps_plain(isf_lattice *lat, uint64_t n) {
 }
 
 constexpr uint32_t kGraphSweeps = 64;
+constexpr uint32_t kTailGraphMin = 16;  // shorter remainders run as plain launches
 
 void drop_graph(isf_lattice *lat) {
     if (lat->graph) {
         (void)hipGraphExecDestroy(lat->graph);
         lat->graph = nullptr;
     }
+    if (lat->tail_graph) {
+        (void)hipGraphExecDestroy(lat->tail_graph);
+        lat->tail_graph = nullptr;
+    }
 }
 
-int32_t build_graph(isf_lattice *lat) {
-    drop_graph(lat);
+bool same_tiling(const Tiling &a, const Tiling &b) {
+    return a.tx == b.tx && a.ty == b.ty && a.ry == b.ry && a.kernel == b.kernel;
+}
+
+// Capture `sweeps` sweeps of plain launches into an executable graph.  A
+// whole-sweep capture must hold an even number of sweeps and start on the main
+// spin copy: the launches alternate the two copies, and every replay starts
+// where the capture did.
+int32_t capture_graph(isf_lattice *lat, uint32_t sweeps, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(lat->stream, hipStreamCaptureModeThreadLocal));
-    int32_t rc = enqueue_sweeps_plain(lat, kGraphSweeps);
+    int32_t rc = enqueue_sweeps_plain(lat, sweeps);
     hipError_t e = hipStreamEndCapture(lat->stream, &g);
     if (rc) {
         if (g)
@@ -384,14 +402,35 @@ int32_t build_graph(isf_lattice *lat) {
     }
     if (e != hipSuccess)
         return fail(ISF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&lat->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        lat->graph = nullptr;
+        *out = nullptr;
         return fail(ISF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
+    return ISF_OK;
+}
+
+int32_t build_graph(isf_lattice *lat) {
+    drop_graph(lat);
+    int32_t rc = capture_graph(lat, kGraphSweeps, &lat->graph);
+    if (rc)
+        return rc;
     lat->graph_sweeps = kGraphSweeps;
     lat->graph_tiling = lat->tiling;
+    return ISF_OK;
+}
+
+int32_t build_tail_graph(isf_lattice *lat, uint32_t sweeps) {
+    if (lat->tail_graph) {
+        (void)hipGraphExecDestroy(lat->tail_graph);
+        lat->tail_graph = nullptr;
+    }
+    int32_t rc = capture_graph(lat, sweeps, &lat->tail_graph);
+    if (rc)
+        return rc;
+    lat->tail_sweeps = sweeps;
+    lat->tail_tiling = lat->tiling;
     return ISF_OK;
 }
 
@@ -410,8 +449,7 @@ int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
         return rc0;
     }
     if (lat->use_graph && lat->stream && n >= kGraphSweeps) {
-        if (!lat->graph || lat->graph_tiling.tx != lat->tiling.tx || lat->graph_tiling.ty != lat->tiling.ty ||
-            lat->graph_tiling.ry != lat->tiling.ry || lat->graph_tiling.kernel != lat->tiling.kernel) {
+        if (!lat->graph || !same_tiling(lat->graph_tiling, lat->tiling)) {
             int32_t rc = build_graph(lat);
             if (rc)
                 return rc;
@@ -420,6 +458,17 @@ int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
             HIP_TRY(hipGraphLaunch(lat->graph, lat->stream));
             n -= lat->graph_sweeps;
         }
+    }
+    // the remainder: a graph of exactly that many sweeps, cached for the next
+    // request of the same length (whole-sweep graphs need an even count)
+    if (lat->use_graph && lat->stream && n >= kTailGraphMin && (n % 2 == 0 || !is_whole(lat->tiling.kernel))) {
+        if (!lat->tail_graph || lat->tail_sweeps != n || !same_tiling(lat->tail_tiling, lat->tiling)) {
+            int32_t rc = build_tail_graph(lat, (uint32_t)n);
+            if (rc)
+                return rc;
+        }
+        HIP_TRY(hipGraphLaunch(lat->tail_graph, lat->stream));
+        n = 0;
     }
     return enqueue_sweeps_plain(lat, n);
 }
@@ -1175,6 +1224,37 @@ int32_t isf_surface_image(isf_lattice *lat, int8_t *img_dev, uint64_t bytes) {
     hipError_t e = launch_surface_image(lat->L, cur, img_dev, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "surface image launch: %s", hipGetErrorString(e));
+    return ISF_OK;
+}
+
+int32_t isf_draw_xor(isf_lattice *lat, uint32_t t0, uint32_t n_sweeps, uint32_t *xor_dev, float *ms) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!xor_dev || n_sweeps == 0)
+        return fail(ISF_EINVAL, "null checksum buffer or no sweeps");
+    if ((rc = set_device_of(lat)))
+        return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    if (hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ISF_EHIP, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(e0, lat->stream);
+    hipError_t e = launch_draw_xor(lat->L, t0, n_sweeps, xor_dev, lat->n_cu, lat->stream);
+    (void)hipEventRecord(e1, lat->stream);
+    float m = 0.f;
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(lat->stream);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&m, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return fail(ISF_EHIP, "draw ceiling: %s", hipGetErrorString(e));
+    if (ms)
+        *ms = m;
     return ISF_OK;
 }
 

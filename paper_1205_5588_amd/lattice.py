@@ -199,6 +199,18 @@ class Lattice:
         check(_lib.load().isf_time_launches(self.handle, int(n_sweeps), ms, ctypes.byref(n)))
         return [float(v) for v in ms], int(n.value)
 
+    def draw_xor(self, t0: int, n_sweeps: int) -> Tuple[int, float]:
+        """Draw-only ceiling: every stored dword draws its attempt's Philox numbers for
+        sweeps t0 .. t0 + n_sweeps - 1 and nothing else; returns (XOR of all words drawn,
+        milliseconds of the launch).  The film is not changed."""
+        torch = _torch()
+        out = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ms = ctypes.c_float()
+        check(_lib.load().isf_draw_xor(self.handle, int(t0) & 0xFFFFFFFF, int(n_sweeps), out.data_ptr(),
+                                       ctypes.byref(ms)))
+        return int(out.cpu().item()) & 0xFFFFFFFF, float(ms.value)
+
     # ------------------------------------------------------------------ state
     def observables(self) -> dict:
         o = Obs()

@@ -782,3 +782,27 @@ def test_aniso_rejected_where_unsupported(isf):
     assert g.advance(2) == 2
     o.run(2.0, 10, 2)
     _assert_same(g, o)
+
+
+# ------------------------------------------------------------------ draw-only ceiling
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_draw_ceiling_checksum_equals_oracle_generator(isf, fmt):
+    """The draw-only kernel draws, for every stored dword and sweep, the numbers of that
+    dword's attempt: its XOR checksum equals the oracle's Philox over the same counters."""
+    X, Y, Z = (72, 10, 3) if fmt == 0 else (128, 6, 2)
+    h = _rand_h((Y, X), Z, 3)
+    seed, rep = 0x1234_5678_9ABC_DEF0, 9
+    g = isf.Lattice(h, Z, seed, replica=rep, fmt=fmt)
+    _say("draw ceiling fmt", fmt)
+    x, ms = g.draw_xor(0xFFFFFFFE, 3)   # the sweep counter wraps in word 1 of the counter
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    want = 0
+    for t in (0xFFFFFFFE, 0xFFFFFFFF, 0):
+        for z in range(Z):
+            for y in range(Y):
+                sigma = (y & 1) + 2 * (z & 1)
+                for d in range(X // 8):
+                    for w in cpu.philox(((z * Y + y) * (X // 8) + d, t, rep, sigma), key):
+                        want ^= w
+    assert x == want and ms > 0
+    np.testing.assert_array_equal(g.spins(), cpu.Film(h, Z, seed, rep).spins())  # the film is untouched
