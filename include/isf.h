@@ -325,6 +325,26 @@ int32_t isf_draw_xor(isf_lattice *lat, uint32_t t0, uint32_t n_sweeps, uint32_t 
  * values); used to check the incremental bookkeeping.  Synchronous. */
 int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E_bond);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the full recount of isf_recount for n
+ * films given only their spin buffers, with no lattice handle and no aux
+ * buffer.  descs[i] describes film i and spins_dev[i] is its device spin
+ * buffer in the library's layout (isf_lattice_bytes), holding the current
+ * spins: always so with the per-sublattice kernels, and after isf_read_spins
+ * or isf_recount with the whole-sweep kernels, which may leave them in their
+ * second copy until then.  Writes out[4 i ..
+ * 4 i + 3] = {M, E_bond, N_occ, N_bonds} for film i (host memory, n x 4
+ * int64).  The counters live in a fixed device array of the library, one per
+ * GPU, reached through its symbol address: the call allocates nothing.  It
+ * runs on the calling thread's current device, on `stream` (null: the null
+ * stream), and synchronises that stream.  The counters are shared by every
+ * call on one GPU: calls that overlap on one GPU race and give wrong counts.
+ * Errors: ISF_ENOSPC for n > ISF_RECOUNT_MAX_FILMS; ISF_EINVAL for null
+ * pointers or an invalid description. */
+#define ISF_RECOUNT_MAX_FILMS 1024u
+int32_t isf_recount_films(const isf_desc *descs, const void *const *spins_dev, uint32_t n, void *stream,
+                          int64_t *out);
+
 #ifdef __cplusplus
 }
 #endif

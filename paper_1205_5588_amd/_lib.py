@@ -100,6 +100,8 @@ EXPORTS = {
     "isf_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.POINTER(Step)), ctypes.POINTER(ctypes.c_uint32),
                                        ctypes.POINTER(ctypes.POINTER(Record)), ctypes.c_int32]),
+    "isf_recount_films": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "isf_draw_xor": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_float)]),
     "isf_time_launches": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),

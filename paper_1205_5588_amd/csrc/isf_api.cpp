@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1287,6 +1288,101 @@ int32_t isf_recount(isf_lattice *lat, int64_t *M, int64_t *E) {
         return rc;
     *M = cnt[0];
     *E = -cnt[1] / 2;
+    return ISF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// recount without allocation
+
+// The counters of isf_recount_films: four int64 per film (M, sum_i s_i n_i,
+// occupied sites, occupied neighbours), at most ISF_RECOUNT_MAX_FILMS films.
+// Each GPU the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in: the device address comes
+// from hipGetSymbolAddress, per device, and only that address is used.
+static __device__ __align__(256) int64_t scratch[4 * ISF_RECOUNT_MAX_FILMS];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+int64_t *g_scratch_dev[kScratchDevices];  // per device; null until its first call
+
+// The device address of `scratch` on device `dev` (the current device).
+int32_t scratch_on(int dev, int64_t **out) {
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(ISF_EINVAL, "device %d outside the %d devices the recount counters cover", dev,
+                    kScratchDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ISF_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<int64_t *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return ISF_OK;
+}
+
+// A fill kernel rather than hipMemsetAsync, so that the call could be captured.
+__global__ void k_zero_counters(int64_t *p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t isf_recount_films(const isf_desc *descs, const void *const *spins_dev, uint32_t n, void *stream,
+                          int64_t *out) {
+    if (n > ISF_RECOUNT_MAX_FILMS)
+        return fail(ISF_ENOSPC, "%u films exceed the %u the recount counters hold", n,
+                    (unsigned)ISF_RECOUNT_MAX_FILMS);
+    if (n == 0)
+        return ISF_OK;
+    if (!descs || !spins_dev || !out)
+        return fail(ISF_EINVAL, "null pointer argument");
+    for (uint32_t i = 0; i < n; ++i) {
+        int32_t rc = validate_desc(&descs[i]);
+        if (rc)
+            return rc;
+        if (!spins_dev[i])
+            return fail(ISF_EINVAL, "null spin buffer %u", i);
+    }
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    int64_t *cnt = nullptr;
+    int32_t rc = scratch_on(dev, &cnt);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_counters, dim3((4 * n + 255) / 256), dim3(256), 0, s, cnt, 4 * n);
+    HIP_TRY(hipGetLastError());
+    for (uint32_t i = 0; i < n; ++i) {
+        const isf_desc &d = descs[i];
+        LatDev L{};
+        L.spins = static_cast<uint8_t *>(const_cast<void *>(spins_dev[i]));
+        L.X = d.X;
+        L.Y = d.Y;
+        L.Z = d.Z;
+        L.W = d.X / 2;
+        L.nd = d.format == ISF_FORMAT_INT8 ? L.W / 4 : L.W / 32;
+        L.format = d.format;
+        const hipError_t e = d.format == ISF_FORMAT_INT8 ? launch_recount_i8(L, cnt + 4 * i, s)
+                                                         : launch_recount_bp(L, cnt + 4 * i, s);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "recount launch %u: %s", i, hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(out, cnt, sizeof(int64_t) * 4 * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < n; ++i) {
+        int64_t *o = out + 4 * i;
+        o[1] = -o[1] / 2;  // E_bond = -(1/2) sum_i s_i n_i
+        o[3] /= 2;         // each bond seen from both ends
+    }
     return ISF_OK;
 }
 
