@@ -762,6 +762,40 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// The block's sums of M, E_bond and accepted flips into a slot (as
+// finish_block_to), behind a barrier that waits for LDS only and with no
+// barrier after the slot atomics: for the end of a kernel, where nothing
+// reuses the reduction array.
+template <int NT>
+__device__ __forceinline__ void finish_block_lds(Slot *slots, int dM, int dE, int acc, uint32_t block_in_lat) {
+    __shared__ int red[3][NT / 64];
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    dM = wave_sum(dM);
+    dE = wave_sum(dE);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        red[0][wid] = dM;
+        red[1][wid] = dE;
+        red[2][wid] = acc;
+    }
+    lds_barrier();
+    if (threadIdx.x == 0) {
+        int64_t sM = 0, sE = 0, sA = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+            sM += red[0][w];
+            sE += red[1][w];
+            sA += red[2][w];
+        }
+        if (sA) {
+            Slot *slot = &slots[block_in_lat % kSlots];
+            aadd(&slot->dM, sM);
+            aadd(&slot->dE, sE);
+            aadd(&slot->acc, sA);
+        }
+    }
+}
+
 // Lists of the pipelined kernel: per tile the four counts, then the four lists
 // packed (each padded to a multiple of 8 entries).  One block per tile; a
 // counting pass fixes the offsets, a second pass writes the entries.
@@ -1114,24 +1148,26 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     constexpr uint32_t TX4 = TXD / 4, kPiecesPerPlane = TX4 * TYR, kPlaneStep = NT / kPiecesPerPlane;
     static_assert(NT % kPiecesPerPlane == 0, "a block covers whole planes of a tile");
     const uint32_t wb_cx = 4 * (tid % TX4), wb_ry = (tid / TX4) % TYR, wb_p0 = tid / kPiecesPerPlane + 1;
-    auto write_back = [&](uint32_t tile, uint32_t buf, uint32_t slot) {
+    // n_prev, e_prev: the tile's change list of the previous sweep (its count, and
+    // entry `tid` where tid < the count), loaded into registers when the tile
+    // started so that the write-back waits for no memory round trip.
+    static_assert(kChgCap <= NT, "one previous change per thread");
+    auto write_back = [&](uint32_t tile, uint32_t buf, uint32_t slot, uint32_t n_prev, uint32_t e_prev) {
         const uint32_t bx = tile % nbx, by = tile / nbx;
         const uint32_t *Rt = R + buf * (Z + 1) * PL;
         uint8_t *chg_rec = lists + (size_t)tile * recb + G::chg_off(Z);
-        const uint32_t *prev = reinterpret_cast<const uint32_t *>(chg_rec + (1u - q) * kChgRecBytes);
         uint32_t *cur = reinterpret_cast<uint32_t *>(chg_rec + q * kChgRecBytes);
-        const uint32_t n_cur = chg_n_sh[slot], n_prev = prev[0];
+        const uint32_t n_cur = chg_n_sh[slot];
         if (n_cur <= kChgCap && n_prev <= kChgCap) {
             auto put = [&](uint32_t qi) {  // listed dwords are the tile's own
                 const uint32_t p = qi / PL, rem = qi - p * PL, ry = rem / RX, cx = rem - ry * RX;
                 const uint32_t y = by * TYR + ry - kHY, d = bx * TXD + cx - kPX;
                 *reinterpret_cast<uint32_t *>(out + (p * planeb + y * rowb + d * 4u)) = Rt[qi];
             };
-            const uint16_t *pe = reinterpret_cast<const uint16_t *>(prev + 1);
             for (uint32_t i = tid; i < n_cur; i += NT)
                 put(chg_sh[slot][i]);
-            for (uint32_t i = tid; i < n_prev; i += NT)
-                put(pe[i]);
+            if (tid < n_prev)
+                put(e_prev);
         } else {
             const uint32_t y = by * TYR + wb_ry, d = bx * TXD + wb_cx;
             if (y < Y && d < nd) {  // else: a ragged tile's part beyond the film
@@ -1151,19 +1187,16 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
             cur[0] = n_cur <= kChgCap ? n_cur : kChgAll;
     };
 
-    BookNext bn{};
-    uint32_t k = 0;
-    for (; k < kmax; ++k) {
-        const uint32_t tile = k ? my_tiles[k] : t0;  // my_tiles is read after the first tile's barriers
-        if (tile == kNoTile)  // uniform
-            break;
-        const uint32_t buf = k & 1u;
-        // this tile's loads (and the write-back of two tiles ago) have landed
-        __builtin_amdgcn_s_waitcnt(0);
-        if (prev != 0xFFFFFFFFu)
-            write_back(prev, buf ^ 1u, buf ^ 1u);
-        if (tid == 0)
-            chg_n_sh[buf] = 0;  // list slot of this tile (its last user, two tiles ago, is written back)
+    // A tile's change list of the previous sweep, for its write-back: the count
+    // (an atomic load, so that it is a vector load and not a scalar one that every
+    // LDS wait of the phases would then wait for) and entry `tid`.
+    auto prev_changes = [&](uint32_t tile, uint32_t &n, uint32_t &e) {
+        const uint8_t *rec = lists + (size_t)tile * recb + G::chg_off(Z) + (1u - q) * kChgRecBytes;
+        n = ald(reinterpret_cast<const uint32_t *>(rec));
+        e = tid < kChgCap ? (uint32_t)reinterpret_cast<const uint16_t *>(rec + 4)[tid] : 0u;
+    };
+    // Philox counter base and tile flags of every region row and dword of a tile.
+    auto build_tables = [&](uint32_t tile) {
         const uint32_t bx = tile % nbx, by = tile / nbx;
         const int d0 = (int)(bx * TXD), y0 = (int)(by * TYR);
         const uint32_t ynd = Y * nd;
@@ -1184,6 +1217,27 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
                 dmap[c] = (uint32_t)d | (own ? 0x80000000u : 0u);
             }
         }
+    };
+
+    // the first tile's tables while its loads are in flight
+    if (t0 != kNoTile)
+        build_tables(t0);
+    uint32_t pn_prev = 0, pe_prev = 0;  // change list of the tile whose write-back is pending
+    BookNext bn{};
+    uint32_t k = 0;
+    for (; k < kmax; ++k) {
+        const uint32_t tile = k ? my_tiles[k] : t0;  // my_tiles is read after the first tile's barriers
+        if (tile == kNoTile)  // uniform
+            break;
+        const uint32_t buf = k & 1u;
+        // this tile's loads (and the write-back of two tiles ago) have landed
+        __builtin_amdgcn_s_waitcnt(0);
+        if (prev != 0xFFFFFFFFu) {
+            write_back(prev, buf ^ 1u, buf ^ 1u, pn_prev, pe_prev);
+            build_tables(tile);  // the previous tile's phases, its readers, have ended
+        }
+        if (tid == 0)
+            chg_n_sh[buf] = 0;  // list slot of this tile (its last user, two tiles ago, is written back)
         if (k == 0) {
             if (tid < 64) {
                 tab64[tid] = pro_tab;
@@ -1209,6 +1263,9 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         const uint32_t nxt = k + 1 < kmax ? my_tiles[k + 1] : kNoTile;
         if (nxt != kNoTile)
             issue(nxt, buf ^ 1u);
+        // after the block's last full barrier of the tile, so that the load lands
+        // while the tile is swept (a full barrier would wait for it)
+        prev_changes(tile, pn_prev, pe_prev);
         prev = tile;
         if (!run_sh) {  // uniform: the schedule is finished; nothing flips
             lds_barrier();
@@ -1231,17 +1288,20 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
         pipe_phase<3, RX, PL, NT>(lb + l3, cnt.w, f3, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg_sh[buf], &chg_n_sh[buf], dM, dE, acc);
         lds_barrier();
     }
-    if (prev != 0xFFFFFFFFu)
-        write_back(prev, (k - 1u) & 1u, (k - 1u) & 1u);
     if (k == 0 && booker) {  // a block without tiles (never block 0)
         book_stage(bk, br, tid);
         bn = book_next_issue(L, bk, tid);
     }
-    finish_block_to<NT>(slots_of(L, q), dM, dE, acc, blockIdx.x);
+    // the sweep's slot sums and books first, with barriers that wait for LDS
+    // only: the slot atomics and the last write-back's stores are then in
+    // flight together, and no wave waits for either
+    finish_block_lds<NT>(slots_of(L, q), dM, dE, acc, blockIdx.x);
     if (booker) {
         book_fold(L, 1 - q, bk, tid);
         book_advance_pre(L, q, bk, cur_tab, bn.tab, bn.ns, bn.nd, tid);
     }
+    if (prev != 0xFFFFFFFFu)
+        write_back(prev, (k - 1u) & 1u, (k - 1u) & 1u, pn_prev, pe_prev);
 }
 
 namespace {
