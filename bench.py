@@ -265,7 +265,7 @@ def bench_batched(args):
     attempts = sum(n * len(hnums) * spst for n in n_occ)
     out = {"value": round(attempts / dt, 1), "unit": "spin-flip attempts/s", "replicas": len(reps),
            "sweeps_per_replica": len(hnums) * spst, "attempts": attempts, "seconds": round(dt, 4),
-           "mode": {0: "phase_launch", 1: "persistent", 2: "whole_sweep"}[tuned["mode"]], "tiling": tuned["tiling"],
+           "mode": {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[tuned["mode"]], "tiling": tuned["tiling"],
            "tuning": tuned["all"]}
     # the same replicas one after another through the plain path (a sample, shortened schedule)
     sample = list(range(0, len(reps), 16))
@@ -321,7 +321,7 @@ def bench_serving(args, reqs, hmap):
     s = stats.summary()
     s["wall_s"] = round(wall, 2)
     s["offered_attempts_per_s"] = round(s["attempts"] / args.serve_duration, 1)
-    s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep"}[args.serve_mode]
+    s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[args.serve_mode]
     s["arrivals"] = "Poisson 50 req/s for %g s" % args.serve_duration
     return s
 

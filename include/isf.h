@@ -271,8 +271,13 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
  * runs the whole sweep of every lattice with the whole-sweep kernel
  * (ISF_KERNEL_SWEEP), in the shape of lats[0]'s tuning if it selects that
  * kernel, else 16 x 16 with 4 waves (EINVAL if that shape's LDS does not fit
- * the deepest film).  Each lattice's trajectory is identical to running it
- * alone.
+ * the deepest film); in ISF_BATCH_PIPE mode (INT8 lattices) one launch per
+ * sweep runs the pipelined whole-sweep kernel (ISF_KERNEL_PIPE, 32 x 32 tiles
+ * with 16 waves) over every lattice it can take -- rows of at least 40
+ * dwords (X >= 320), at least 40 rows, planes that fit its LDS (Z <= 8) --
+ * each with its own share of the blocks (about 8 tiles per block), and the
+ * others in the ISF_BATCH_PHASE_LAUNCH way.  Each lattice's
+ * trajectory is identical to running it alone.
  *
  * A batch context owns a pinned host staging area for its launch table and
  * uses the caller's device workspace (isf_batch_workspace_bytes) for the
@@ -282,7 +287,7 @@ int32_t isf_schedule_records(isf_lattice *lat, isf_record *out, uint32_t n);
  * remaining sweeps) and returns without waiting; isf_batch_sync waits.
  * EINVAL for a lattice whose loaded schedule has the anisotropy term (its
  * phases need the film's own M, see isf_step.an_num). */
-enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1, ISF_BATCH_WHOLE = 2 };
+enum { ISF_BATCH_PHASE_LAUNCH = 0, ISF_BATCH_PERSISTENT = 1, ISF_BATCH_WHOLE = 2, ISF_BATCH_PIPE = 3 };
 
 typedef struct isf_batch isf_batch;
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libisf.so")
 ISF_OK, ISF_EINVAL, ISF_ENOSPC, ISF_EHIP, ISF_ESTATE = 0, -1, -2, -3, -4
 FORMAT_INT8, FORMAT_BITPACK = 0, 1
 INIT_UP, INIT_DOWN, INIT_RANDOM = 0, 1, 2
-BATCH_PHASE_LAUNCH, BATCH_PERSISTENT, BATCH_WHOLE = 0, 1, 2
+BATCH_PHASE_LAUNCH, BATCH_PERSISTENT, BATCH_WHOLE, BATCH_PIPE = 0, 1, 2, 3
 MAX_STEPS = 1024
 
 

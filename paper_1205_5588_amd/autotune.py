@@ -19,7 +19,8 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, BATCH_WHOLE, FORMAT_BITPACK, FORMAT_INT8, KERNEL_LIST,
+from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, BATCH_PIPE, BATCH_WHOLE, FORMAT_BITPACK, FORMAT_INT8,
+                   KERNEL_LIST,
                    KERNEL_PIPE, KERNEL_SWEEP, KERNEL_TILES, IsfError)
 
 TILINGS = {
@@ -55,7 +56,7 @@ def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
     2048^2 x 8, the single-tile kernel with 16 x 16 tiles on small films such
     as 512^2 x 5); others take the sublattice tiles."""
     if fmt == FORMAT_INT8 and Z <= 8:
-        if X // 8 >= 256 and Y >= 512 and X % 32 == 0:
+        if X // 8 >= 256 and Y >= 512:
             return (32, 32, 16, True, KERNEL_PIPE)
         return (16, 16, 4, True, KERNEL_SWEEP)
     return default_tiling(X, fmt) + (True, KERNEL_TILES)
@@ -147,8 +148,11 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
             "ms_per_sweep": best["ms_per_sweep"], "all": timings}
 
 
+# (tile_x, tile_y, rows or waves, batch mode); in the pipelined mode the shape is
+# that of the films the pipelined kernel cannot take (sublattice launches)
 BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH), (16, 16, 4, BATCH_WHOLE),
-                    (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE)]
+                    (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE), (64, 4, 2, BATCH_PIPE),
+                    (32, 8, 2, BATCH_PIPE)]
 
 
 def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list], fmt: int,
@@ -159,7 +163,7 @@ def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list]
 
     from .lattice import Batch
 
-    cands = [c for c in (candidates or BATCH_CANDIDATES) if fmt == FORMAT_INT8 or c[3] != BATCH_WHOLE]
+    cands = [c for c in (candidates or BATCH_CANDIDATES) if fmt == FORMAT_INT8 or c[3] not in (BATCH_WHOLE, BATCH_PIPE)]
     timings = []
     ref = None
     for tx, ty, r, mode in cands:

@@ -41,6 +41,11 @@ hipError_t launch_whole_flush(const LatDev &L, uint32_t q_last, hipStream_t s);
 hipError_t launch_sweep_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
 uint32_t pipe_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t pipe_static_lds(uint32_t tx, uint32_t ty, uint32_t nt);
+uint32_t pipe_batch_static_lds(uint32_t tx, uint32_t ty, uint32_t nt);
+bool pipe_grid(const LatDev &L, uint32_t tx, uint32_t ty, uint32_t cap, uint32_t *nbx, uint32_t *tiles,
+               uint32_t *blocks, uint32_t *kmax);
+hipError_t launch_sweep_i8_pipe_batch(const PipeEntry *ents, const uint32_t *begins, uint32_t n_ents,
+                                      uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s);
 uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t pipe_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
 hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, uint32_t n_cu, hipStream_t s);
@@ -228,6 +233,7 @@ struct isf_lattice {
     uint8_t *lists;
     bool lists_ready;
     Tiling lists_tiling;
+    uint32_t lists_blocks;  // pipelined kernel: the block cap its tile order was built for
     // a run of whole-sweep launches is open: the schedule position lives in the
     // parity-buffered positions until k_whole_flush hands it back
     bool whole_active;
@@ -277,20 +283,28 @@ int32_t launch_end(const isf_lattice *lat) {
 // The spare copy gets the film's layout (its vacancies) once, before its
 // first use; after a whole sweep the state may sit in the spare copy, and
 // settle() moves it back before anything else reads or writes the spins.
-int32_t prepare_spare(isf_lattice *lat, const Tiling &tl) {
+// cap: for the pipelined kernel, the most blocks a sweep of this film uses (its
+// tile order is built for that count): the device's compute units when the
+// film runs alone, its share of a batched launch otherwise.
+int32_t prepare_spare(isf_lattice *lat, const Tiling &tl, uint32_t cap = 0) {
     if (!lat->spare_ready) {
         HIP_TRY(hipMemcpyAsync(lat->spare, lat->L.spins, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice,
                                lat->stream));
         lat->spare_ready = true;
     }
+    const bool pipe = tl.kernel == ISF_KERNEL_PIPE;
+    if (!cap)
+        cap = lat->n_cu;
     const Tiling &lt = lat->lists_tiling;
-    if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty || lt.kernel != tl.kernel) {
-        hipError_t e = tl.kernel == ISF_KERNEL_PIPE ? launch_pipe_lists(lat->L, tl, lat->lists, lat->n_cu, lat->stream)
-                                                    : launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
+    if (!lat->lists_ready || lt.tx != tl.tx || lt.ty != tl.ty || lt.kernel != tl.kernel ||
+        (pipe && lat->lists_blocks != cap)) {
+        hipError_t e = pipe ? launch_pipe_lists(lat->L, tl, lat->lists, cap, lat->stream)
+                            : launch_sweep_lists(lat->L, tl, lat->lists, lat->stream);
         if (e != hipSuccess)
             return fail(ISF_EHIP, "list launch failed: %s", hipGetErrorString(e));
         lat->lists_ready = true;
         lat->lists_tiling = tl;
+        lat->lists_blocks = cap;
     }
     return ISF_OK;
 }
@@ -305,6 +319,32 @@ int32_t prime_whole(isf_lattice *lat) {
             return fail(ISF_EHIP, "prime launch failed: %s", hipGetErrorString(e));
         lat->whole_active = true;
     }
+    return ISF_OK;
+}
+
+// Whether the pipelined kernel of shape tl can sweep this film when its LDS is
+// sized for Zlds planes (Zlds >= the film's Z; a batch sizes it for its deepest
+// film): ISF_OK or the reason (ISF_EINVAL, with the message set).
+int32_t pipe_fits(const isf_lattice *lat, const Tiling &tl, uint32_t Zlds, bool batched) {
+    const uint32_t nd = lat->d.X / 8, Y = lat->d.Y, Z = lat->d.Z;
+    const uint32_t lds = pipe_lds_bytes(tl.tx, tl.ty, Zlds);
+    if (lds == 0 || (tl.ry != 8 && tl.ry != 16))
+        return fail(ISF_EINVAL, "unsupported pipelined shape %ux%u with %u waves", tl.tx, tl.ty, tl.ry);
+    // a region (tile and halo) within one period of the film along x and y
+    if (nd < tl.tx + 8 || Y < tl.ty + 8)
+        return fail(ISF_EINVAL, "pipelined shape %ux%u needs X/8 >= %u and Y >= %u", tl.tx, tl.ty, tl.tx + 8,
+                    tl.ty + 8);
+    // compact dword indices below 2^31 (bit 31 flags the tile's rows) and plane offsets within 32 bits
+    if ((uint64_t)Z * Y * nd >= (1ull << 31) || (uint64_t)(Z + 2) * Y * nd * 4 >= (1ull << 32))
+        return fail(ISF_EINVAL, "film too large for the pipelined kernel");
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
+    const uint32_t st = batched ? pipe_batch_static_lds(tl.tx, tl.ty, 64u * tl.ry)
+                                : pipe_static_lds(tl.tx, tl.ty, 64u * tl.ry);
+    const uint64_t need = (uint64_t)lds + st;
+    if (need > (uint64_t)max_lds || pipe_region_dwords(tl.tx, tl.ty, Zlds) > 65536u)
+        return fail(ISF_EINVAL, "pipelined shape %ux%u needs %llu bytes of LDS for Z = %u (limit %d)", tl.tx, tl.ty,
+                    (unsigned long long)need, Zlds, max_lds);
     return ISF_OK;
 }
 
@@ -719,23 +759,9 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
     } else if (tl.kernel == ISF_KERNEL_PIPE) {
         if (lat->d.format != ISF_FORMAT_INT8 || !lat->spare)
             return fail(ISF_EINVAL, "the pipelined whole-sweep kernel needs an INT8 film");
-        const uint32_t nd = lat->d.X / 8, Y = lat->d.Y, Z = lat->d.Z;
-        const uint32_t lds = pipe_lds_bytes(tl.tx, tl.ty, Z);
-        if (lds == 0 || (tl.ry != 8 && tl.ry != 16))
-            return fail(ISF_EINVAL, "unsupported pipelined shape %ux%u with %u waves", tl.tx, tl.ty, tl.ry);
-        // 16-byte region pieces: rows of whole pieces, at least one region wide and high
-        if (nd % 4 != 0 || nd < tl.tx + 8 || Y < tl.ty + 8)
-            return fail(ISF_EINVAL, "pipelined shape %ux%u needs X a multiple of 32, X/8 >= %u and Y >= %u", tl.tx,
-                        tl.ty, tl.tx + 8, tl.ty + 8);
-        // compact dword indices below 2^31 (bit 31 flags the tile's rows) and plane offsets within 32 bits
-        if ((uint64_t)Z * Y * nd >= (1ull << 31) || (uint64_t)(Z + 2) * Y * nd * 4 >= (1ull << 32))
-            return fail(ISF_EINVAL, "film too large for the pipelined kernel");
-        int max_lds = 0;
-        HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
-        const uint64_t need = (uint64_t)lds + pipe_static_lds(tl.tx, tl.ty, 64u * tl.ry);
-        if (need > (uint64_t)max_lds || pipe_region_dwords(tl.tx, tl.ty, Z) > 65536u)
-            return fail(ISF_EINVAL, "pipelined shape %ux%u needs %llu bytes of LDS for Z = %u (limit %d)", tl.tx,
-                        tl.ty, (unsigned long long)need, Z, max_lds);
+        int32_t rc = pipe_fits(lat, tl, lat->d.Z, false);
+        if (rc)
+            return rc;
     } else if (tl.kernel != ISF_KERNEL_TILES) {
         return fail(ISF_EINVAL, "unknown kernel %u", tl.kernel);
     } else {
@@ -1393,15 +1419,19 @@ int32_t isf_recount_films(const isf_desc *descs, const void *const *spins_dev, u
 
 namespace {
 
-// Batch workspace on the device: the launch table, the first block of every
-// film (whole-sweep mode), then the persistent kernel's barrier words.
+// Batch workspace on the device (and the same regions of the pinned host
+// staging area): the sublattice launch table, the whole-sweep or pipelined
+// launch table, the first block of every film of that table, then the
+// persistent kernel's barrier words.
 struct WsLayout {
-    uint64_t begins, barrier, total;
+    uint64_t phase, table, begins, barrier, total;
 };
 WsLayout ws_layout(uint32_t max_lats) {
     auto up = [](uint64_t v) { return (v + 255) / 256 * 256; };
     WsLayout w;
-    w.begins = up(std::max(sizeof(BatchEntry), sizeof(WholeEntry)) * max_lats);
+    w.phase = 0;
+    w.table = up(sizeof(BatchEntry) * max_lats);
+    w.begins = w.table + up(std::max(sizeof(WholeEntry), sizeof(PipeEntry)) * max_lats);
     w.barrier = w.begins + up(sizeof(uint32_t) * ((uint64_t)max_lats + 1));
     w.total = w.barrier + 256;
     return w;
@@ -1474,9 +1504,12 @@ int32_t isf_batch_sync(isf_batch *b) {
     return ISF_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Batched whole-sweep mode: one launch per sweep over the tiles of every film.
+// The caller has waited for the staging area and records b->staged after.
 int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps,
                             uint64_t *enqueued_out) {
     const Tiling tl = lats[0]->tiling.kernel == ISF_KERNEL_SWEEP ? lats[0]->tiling : Tiling{16, 16, 4, ISF_KERNEL_SWEEP};
@@ -1508,9 +1541,8 @@ int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
             return rc;
         HIP_TRY(hipStreamSynchronize(lat->stream));
     }
-    HIP_TRY(hipEventSynchronize(b->staged));  // the staging area may still be read by the previous copy
-    WholeEntry *stage = static_cast<WholeEntry *>(b->staging);
     const WsLayout wl = ws_layout(b->max_lats);
+    WholeEntry *stage = reinterpret_cast<WholeEntry *>(static_cast<uint8_t *>(b->staging) + wl.table);
     uint32_t *stage_begins = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b->staging) + wl.begins);
     uint64_t sweeps = 0;
     uint32_t m = 0, blocks = 0;
@@ -1536,12 +1568,11 @@ int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
         return ISF_OK;
     }
     stage_begins[m] = blocks;
-    WholeEntry *ents = reinterpret_cast<WholeEntry *>(b->ws_dev);
+    WholeEntry *ents = reinterpret_cast<WholeEntry *>(b->ws_dev + wl.table);
     const uint32_t *begins = reinterpret_cast<const uint32_t *>(b->ws_dev + wl.begins);
     HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(WholeEntry) * m, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->ws_dev + wl.begins, stage_begins, sizeof(uint32_t) * (m + 1), hipMemcpyHostToDevice,
                            b->stream));
-    HIP_TRY(hipEventRecord(b->staged, b->stream));
     for (uint64_t g = 0; g < sweeps; ++g) {
         hipError_t e =
             launch_sweep_i8_halo_batch(ents, begins, m, blocks, tl, Zmax, (uint32_t)(g & 1u), b->stream);
@@ -1562,34 +1593,13 @@ int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
     return ISF_OK;
 }
 
-}  // namespace
-
-int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps, int32_t mode,
-                          uint64_t *enqueued_out) {
-    if (!b || (n && !lats))
-        return fail(ISF_EINVAL, "null pointer argument");
-    if (n > b->max_lats)
-        return fail(ISF_EINVAL, "%u lattices exceed the batch capacity %u", n, b->max_lats);
-    if (mode != ISF_BATCH_PHASE_LAUNCH && mode != ISF_BATCH_PERSISTENT && mode != ISF_BATCH_WHOLE)
-        return fail(ISF_EINVAL, "unknown batch mode %d", mode);
-    if (n == 0) {
-        if (enqueued_out)
-            *enqueued_out = 0;
-        return ISF_OK;
-    }
+// One launch per sublattice (or one persistent launch per chunk) over every
+// film.  The caller has waited for the staging area and records b->staged.
+int32_t batch_advance_phase(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps, int32_t mode,
+                            uint64_t *enqueued_out) {
     const uint32_t format = lats[0]->d.format;
     // batches run the one-launch-per-sublattice tiles; other kernels fall back to the default shape
     const Tiling tl = lats[0]->tiling.kernel == ISF_KERNEL_TILES ? lats[0]->tiling : Tiling{64, 4, 2, ISF_KERNEL_TILES};
-    for (uint32_t i = 0; i < n; ++i) {
-        if (!lats[i])
-            return fail(ISF_EINVAL, "null lattice %u", i);
-        if (lats[i]->d.format != format)
-            return fail(ISF_ESTATE, "lattices of a batch must share one format");
-        if (lats[i]->aniso)
-            return fail(ISF_EINVAL, "lattice %u: batches do not run the anisotropy term", i);
-    }
-    if (mode == ISF_BATCH_WHOLE)
-        return batch_advance_whole(b, lats, n, max_sweeps, enqueued_out);
     // batch kernels work on the main copy of the spins
     for (uint32_t i = 0; i < n; ++i)
         if (lats[i]->cur_spare || lats[i]->whole_active) {
@@ -1598,8 +1608,8 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
                 return rc;
             HIP_TRY(hipStreamSynchronize(lats[i]->stream));
         }
-    // the staging area may still be read by the previous copy
-    HIP_TRY(hipEventSynchronize(b->staged));
+    const WsLayout wl = ws_layout(b->max_lats);
+    BatchEntry *stage = reinterpret_cast<BatchEntry *>(static_cast<uint8_t *>(b->staging) + wl.phase);
     uint64_t sweeps = 0;
     uint32_t m = 0, blocks = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -1607,7 +1617,7 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
         const uint64_t rem = lat->sched_total - lat->sched_enqueued;
         if (rem == 0)
             continue;
-        BatchEntry &e = static_cast<BatchEntry *>(b->staging)[m++];
+        BatchEntry &e = stage[m++];
         e.lat = lat->L;
         e.block_begin = blocks;
         if (format == ISF_FORMAT_INT8)
@@ -1622,10 +1632,9 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
             *enqueued_out = 0;
         return ISF_OK;
     }
-    BatchEntry *ents = reinterpret_cast<BatchEntry *>(b->ws_dev);
-    uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + ws_layout(b->max_lats).barrier);
-    HIP_TRY(hipMemcpyAsync(ents, b->staging, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipEventRecord(b->staged, b->stream));
+    BatchEntry *ents = reinterpret_cast<BatchEntry *>(b->ws_dev + wl.phase);
+    uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + wl.barrier);
+    HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
     if (mode == ISF_BATCH_PHASE_LAUNCH) {
         for (uint64_t sw = 0; sw < sweeps; ++sw) {
             for (uint32_t s = 0; s < 4; ++s) {
@@ -1657,6 +1666,130 @@ int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, ui
     }
     if (enqueued_out)
         *enqueued_out = sweeps;
+    return ISF_OK;
+}
+
+// Pipelined mode: every film the pipelined kernel can take (INT8, a region
+// within one period, LDS for the batch's deepest such film) is swept by one
+// launch per sweep over all of them, each film with its own share of the
+// blocks (about kPipeBatchTiles tiles per block, its lists and tile order
+// built for that count); the others run in the sublattice mode.  The caller
+// has waited for the staging area and records b->staged.
+constexpr uint32_t kPipeBatchTiles = 8;
+
+int32_t batch_advance_pipe(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps,
+                           uint64_t *enqueued_out) {
+    std::vector<isf_lattice *> pipe, rest;
+    const Tiling tl{32, 32, 16, ISF_KERNEL_PIPE};
+    uint32_t Zp = 0;  // the deepest film of the pipelined launch sizes its LDS
+    for (uint32_t i = 0; i < n; ++i) {
+        isf_lattice *lat = lats[i];
+        const bool ok =
+            lat->d.format == ISF_FORMAT_INT8 && lat->spare && pipe_fits(lat, tl, lat->d.Z, true) == ISF_OK;
+        (ok ? pipe : rest).push_back(lat);
+        if (ok)
+            Zp = std::max(Zp, lat->d.Z);
+    }
+    uint64_t enq_rest = 0, sweeps = 0;
+    if (!rest.empty()) {
+        int32_t rc = batch_advance_phase(b, rest.data(), (uint32_t)rest.size(), max_sweeps, ISF_BATCH_PHASE_LAUNCH,
+                                         &enq_rest);
+        if (rc)
+            return rc;
+    }
+    const WsLayout wl = ws_layout(b->max_lats);
+    PipeEntry *stage = reinterpret_cast<PipeEntry *>(static_cast<uint8_t *>(b->staging) + wl.table);
+    uint32_t *stage_begins = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b->staging) + wl.begins);
+    uint32_t m = 0, blocks = 0;
+    for (isf_lattice *lat : pipe) {
+        const uint64_t rem = lat->sched_total - lat->sched_enqueued;
+        if (rem == 0)
+            continue;
+        uint32_t nbx = 0, tiles = 0, nb = 0, kmax = 0;
+        pipe_grid(lat->L, tl.tx, tl.ty, 1u, &nbx, &tiles, &nb, &kmax);
+        const uint32_t cap = std::max(1u, (tiles + kPipeBatchTiles - 1) / kPipeBatchTiles);
+        pipe_grid(lat->L, tl.tx, tl.ty, cap, &nbx, &tiles, &nb, &kmax);
+        int32_t rc;
+        if ((rc = prepare_spare(lat, tl, cap)) || (rc = prime_whole(lat)))
+            return rc;
+        HIP_TRY(hipStreamSynchronize(lat->stream));
+        PipeEntry &e = stage[m++];
+        e.lat = lat->L;
+        e.spare = lat->spare;
+        e.lists = lat->lists;
+        e.block_begin = blocks;
+        stage_begins[m - 1] = blocks;
+        e.nbx = nbx;
+        e.ntiles = tiles;
+        e.kmax = kmax;
+        e.po = lat->cur_spare ? 1u : 0u;
+        e.pad = 0;
+        blocks += nb;
+        sweeps = std::max<uint64_t>(sweeps, std::min<uint64_t>(rem, max_sweeps));
+    }
+    if (m && sweeps) {
+        stage_begins[m] = blocks;
+        PipeEntry *ents = reinterpret_cast<PipeEntry *>(b->ws_dev + wl.table);
+        const uint32_t *begins = reinterpret_cast<const uint32_t *>(b->ws_dev + wl.begins);
+        HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(PipeEntry) * m, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->ws_dev + wl.begins, stage_begins, sizeof(uint32_t) * (m + 1),
+                               hipMemcpyHostToDevice, b->stream));
+        for (uint64_t g = 0; g < sweeps; ++g) {
+            hipError_t e = launch_sweep_i8_pipe_batch(ents, begins, m, blocks, tl, Zp, (uint32_t)(g & 1u), b->stream);
+            if (e != hipSuccess)
+                return fail(ISF_EHIP, "batched pipelined launch: %s", hipGetErrorString(e));
+        }
+        for (isf_lattice *lat : pipe) {
+            const uint64_t ran = std::min<uint64_t>(lat->sched_total - lat->sched_enqueued, sweeps);
+            if (ran & 1u)
+                lat->cur_spare = !lat->cur_spare;
+            lat->sched_enqueued += ran;
+        }
+    }
+    if (enqueued_out)
+        *enqueued_out = std::max(sweeps, enq_rest);
+    return ISF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t isf_batch_advance(isf_batch *b, isf_lattice *const *lats, uint32_t n, uint32_t max_sweeps, int32_t mode,
+                          uint64_t *enqueued_out) {
+    if (!b || (n && !lats))
+        return fail(ISF_EINVAL, "null pointer argument");
+    if (n > b->max_lats)
+        return fail(ISF_EINVAL, "%u lattices exceed the batch capacity %u", n, b->max_lats);
+    if (mode != ISF_BATCH_PHASE_LAUNCH && mode != ISF_BATCH_PERSISTENT && mode != ISF_BATCH_WHOLE &&
+        mode != ISF_BATCH_PIPE)
+        return fail(ISF_EINVAL, "unknown batch mode %d", mode);
+    if (n == 0) {
+        if (enqueued_out)
+            *enqueued_out = 0;
+        return ISF_OK;
+    }
+    const uint32_t format = lats[0]->d.format;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!lats[i])
+            return fail(ISF_EINVAL, "null lattice %u", i);
+        if (lats[i]->d.format != format)
+            return fail(ISF_ESTATE, "lattices of a batch must share one format");
+        if (lats[i]->aniso)
+            return fail(ISF_EINVAL, "lattice %u: batches do not run the anisotropy term", i);
+    }
+    // the staging area may still be read by the previous call's copies
+    HIP_TRY(hipEventSynchronize(b->staged));
+    int32_t rc;
+    if (mode == ISF_BATCH_WHOLE)
+        rc = batch_advance_whole(b, lats, n, max_sweeps, enqueued_out);
+    else if (mode == ISF_BATCH_PIPE)
+        rc = batch_advance_pipe(b, lats, n, max_sweeps, enqueued_out);
+    else
+        rc = batch_advance_phase(b, lats, n, max_sweeps, mode, enqueued_out);
+    if (rc)
+        return rc;
+    HIP_TRY(hipEventRecord(b->staged, b->stream));
     return ISF_OK;
 }
 

@@ -143,6 +143,19 @@ struct BatchEntry {
     uint32_t nbx, nby, nbz;  // block grid of this film for the launch's phase
 };
 
+// One film in a batched pipelined launch.
+struct PipeEntry {
+    LatDev lat;
+    uint8_t *spare;        // the film's second spin copy
+    uint8_t *lists;        // its tile records and tile order, built for its block count
+    uint32_t block_begin;  // first linear block of this film
+    uint32_t nbx;          // tiles along a row
+    uint32_t ntiles;       // tiles of the film
+    uint32_t kmax;         // most tiles one of its blocks takes
+    uint32_t po;           // sweep parity of the film at the launch with g = 0
+    uint32_t pad;
+};
+
 // One film in a batched whole-sweep launch.
 struct WholeEntry {
     LatDev lat;

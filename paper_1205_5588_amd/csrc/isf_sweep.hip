@@ -751,6 +751,10 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 __device__ __forceinline__ void load_to_lds16(const void *g, void *lds_wave) {
     __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_wave, 16, 0, 0);
 }
+// The same with 4 bytes per lane: lane l's dword lands at lds_wave + 4 l.
+__device__ __forceinline__ void load_to_lds4(const void *g, void *lds_wave) {
+    __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_wave, 4, 0, 0);
+}
 
 // Workgroup barrier for LDS data only.  __syncthreads() also waits for every
 // vector memory operation in flight, the loads into the other LDS buffer
@@ -1037,10 +1041,12 @@ __device__ __forceinline__ BookNext book_next_issue(const LatDev &L, const BookL
     return b;
 }
 
+// One pipelined sweep of parity q of film L by block `blk` of the film's blocks
+// (the body of the plain and the batched kernels).
 template <int TXD, int TYR, int NT>
-__global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *__restrict__ src,
-                                                      uint8_t *__restrict__ dst, uint8_t *__restrict__ lists,
-                                                      uint32_t nbx, uint32_t ntiles, uint32_t kmax, uint32_t q) {
+__device__ __forceinline__ void pipe_sweep(const LatDev &L, const uint8_t *__restrict__ src,
+                                           uint8_t *__restrict__ dst, uint8_t *__restrict__ lists, uint32_t nbx,
+                                           uint32_t ntiles, uint32_t kmax, uint32_t q, uint32_t blk) {
     using G = GeoP<TXD, TYR>;
     constexpr int RX = G::RX, RYN = G::RYN, PL = G::PL, CH = G::CH;
     extern __shared__ __align__(16) uint8_t smb[];
@@ -1067,7 +1073,7 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     // kNoTile past the last).  The first index is a uniform load issued before
     // anything is stored (a scalar load, which no vector load waits behind) and
     // starts the first tile's loads; the others go to LDS for the tile loop.
-    const uint32_t *order = reinterpret_cast<const uint32_t *>(lists + (size_t)ntiles * recb) + blockIdx.x * kmax;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(lists + (size_t)ntiles * recb) + blk * kmax;
     const uint32_t t0 = order[0];
 
     // Issue the loads of a tile's planes 1..Z and of its whole list record
@@ -1081,20 +1087,39 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     const uint32_t lrow = lane / CH, lcol = lane - lrow * CH;
     auto issue = [&](uint32_t tile, uint32_t buf) {
         const uint32_t bx = tile % nbx, by = tile / nbx;
-        int d = (int)(bx * TXD) - kPX + 4 * (int)lcol;  // within one period of the row (nd >= RX)
-        d += d < 0 ? (int)nd : 0;
-        d -= d >= (int)nd ? (int)nd : 0;
-        const char *col = reinterpret_cast<const char *>(src) + planeb + (uint32_t)d * 4u;  // plane 1
         const int ry0 = (int)(by * TYR) - kHY;
         uint32_t *Rb = R + (buf * (Z + 1) + 1) * PL;  // plane 1 of the buffer
-        for (uint32_t ld = wv; ld < Z * kLoadsPerPlane; ld += NT / 64) {  // uniform
-            const uint32_t p = ld / kLoadsPerPlane, r0 = (ld - p * kLoadsPerPlane) * kRowsPerLoad;
-            const uint32_t ry = r0 + lrow;
-            if (lrow < kRowsPerLoad && ry < (uint32_t)RYN) {
-                int y = ry0 + (int)ry;  // within one period of the film (Y >= RYN)
-                y += y < 0 ? (int)Y : 0;
-                y -= y >= (int)Y ? (int)Y : 0;
-                load_to_lds16(col + (p * planeb + (uint32_t)y * rowb), Rb + (p * RYN + r0) * RX);
+        if ((nd & 3u) == 0) {  // uniform: rows of the film are whole 16-byte pieces
+            int d = (int)(bx * TXD) - kPX + 4 * (int)lcol;  // within one period of the row (nd >= RX)
+            d += d < 0 ? (int)nd : 0;
+            d -= d >= (int)nd ? (int)nd : 0;
+            const char *col = reinterpret_cast<const char *>(src) + planeb + (uint32_t)d * 4u;  // plane 1
+            for (uint32_t ld = wv; ld < Z * kLoadsPerPlane; ld += NT / 64) {  // uniform
+                const uint32_t p = ld / kLoadsPerPlane, r0 = (ld - p * kLoadsPerPlane) * kRowsPerLoad;
+                const uint32_t ry = r0 + lrow;
+                if (lrow < kRowsPerLoad && ry < (uint32_t)RYN) {
+                    int y = ry0 + (int)ry;  // within one period of the film (Y >= RYN)
+                    y += y < 0 ? (int)Y : 0;
+                    y -= y >= (int)Y ? (int)Y : 0;
+                    load_to_lds16(col + (p * planeb + (uint32_t)y * rowb), Rb + (p * RYN + r0) * RX);
+                }
+            }
+        } else {
+            // a 16-byte piece would straddle the periodic seam (or a row end):
+            // every region dword by itself, 64 consecutive region dwords per load
+            const char *base = reinterpret_cast<const char *>(src) + planeb;  // plane 1
+            for (uint32_t ld = wv; ld * 64u < Z * (uint32_t)PL; ld += NT / 64) {  // uniform
+                const uint32_t j = ld * 64u + lane;
+                if (j < Z * (uint32_t)PL) {
+                    const uint32_t p = j / PL, rem = j - p * PL, ry = rem / RX, c = rem - ry * RX;
+                    int y = ry0 + (int)ry;  // within one period of the film (Y >= RYN)
+                    y += y < 0 ? (int)Y : 0;
+                    y -= y >= (int)Y ? (int)Y : 0;
+                    int d = (int)(bx * TXD) - kPX + (int)c;  // within one period of the row (nd >= RX)
+                    d += d < 0 ? (int)nd : 0;
+                    d -= d >= (int)nd ? (int)nd : 0;
+                    load_to_lds4(base + (p * planeb + (uint32_t)y * rowb + (uint32_t)d * 4u), Rb + ld * 64u);
+                }
             }
         }
         const uint8_t *rec = lists + (size_t)tile * recb;
@@ -1115,7 +1140,7 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     // position, its other tiles' indices, the books) is loaded into registers
     // before the first tile's loads are issued and stored to LDS after they
     // have landed: stored at once, each would wait behind them.
-    const bool booker = blockIdx.x == 0 && tid < 64;  // block 0 keeps the books
+    const bool booker = blk == 0 && tid < 64;  // the film's block 0 keeps the books
     BookRegs br;
     uint32_t cur_tab = 0;
     if (booker) {
@@ -1173,10 +1198,20 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
             if (y < Y && d < nd) {  // else: a ragged tile's part beyond the film
                 const uint32_t *from = Rt + (wb_p0 * RYN + wb_ry + kHY) * RX + wb_cx + kPX;
                 char *to = out + (wb_p0 * planeb + y * rowb + d * 4u);
-                for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(from);
-                    if (v.x != kVacant || v.y != kVacant || v.z != kVacant || v.w != kVacant)
-                        *reinterpret_cast<uint4 *>(to) = v;
+                if ((nd & 3u) == 0) {  // uniform: whole 16-byte pieces
+                    for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb) {
+                        const uint4 v = *reinterpret_cast<const uint4 *>(from);
+                        if (v.x != kVacant || v.y != kVacant || v.z != kVacant || v.w != kVacant)
+                            *reinterpret_cast<uint4 *>(to) = v;
+                    }
+                } else {  // rows are not 16-byte aligned: the piece's dwords inside the row, one by one
+                    const uint32_t nj = min(4u, nd - d);
+                    for (uint32_t p = wb_p0; p <= Z; p += kPlaneStep, from += kPlaneStep * PL, to += kPlaneStep * planeb)
+                        for (uint32_t j = 0; j < nj; ++j) {
+                            const uint32_t v = from[j];
+                            if (v != kVacant)
+                                reinterpret_cast<uint32_t *>(to)[j] = v;
+                        }
                 }
             }
         }
@@ -1295,13 +1330,43 @@ __global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *_
     // the sweep's slot sums and books first, with barriers that wait for LDS
     // only: the slot atomics and the last write-back's stores are then in
     // flight together, and no wave waits for either
-    finish_block_lds<NT>(slots_of(L, q), dM, dE, acc, blockIdx.x);
+    finish_block_lds<NT>(slots_of(L, q), dM, dE, acc, blk);
     if (booker) {
         book_fold(L, 1 - q, bk, tid);
         book_advance_pre(L, q, bk, cur_tab, bn.tab, bn.ns, bn.nd, tid);
     }
     if (prev != 0xFFFFFFFFu)
         write_back(prev, (k - 1u) & 1u, (k - 1u) & 1u, pn_prev, pe_prev);
+}
+
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_pipe(LatDev L, const uint8_t *__restrict__ src,
+                                                      uint8_t *__restrict__ dst, uint8_t *__restrict__ lists,
+                                                      uint32_t nbx, uint32_t ntiles, uint32_t kmax, uint32_t q) {
+    pipe_sweep<TXD, TYR, NT>(L, src, dst, lists, nbx, ntiles, kmax, q, blockIdx.x);
+}
+
+// Batched: one launch covers one sweep of every film of a batch.  Film f owns
+// the blocks [begins[f], begins[f + 1]) and sweeps its tiles with them as the
+// plain kernel would with that many blocks (its lists and tile order are built
+// for that count); its sweep parity is (g ^ po_f) & 1 for the launch's sweep
+// index g.  A film past its schedule's end sits the launch out: its blocks
+// copy the state they read, which leaves both copies equal.
+template <int TXD, int TYR, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_i8_pipe_batch(const PipeEntry *__restrict__ ents,
+                                                            const uint32_t *__restrict__ begins, uint32_t n_ents,
+                                                            uint32_t g) {
+    __shared__ uint32_t ent_sh;
+    const uint32_t b = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < n_ents; i += NT)
+        if (begins[i] <= b && b < begins[i + 1])
+            ent_sh = i;  // exactly one film's range holds b
+    __syncthreads();
+    const PipeEntry &e = ents[ent_sh];
+    const uint32_t q = (g ^ e.po) & 1u;
+    uint8_t *main_copy = e.lat.spins, *spare = e.spare;
+    pipe_sweep<TXD, TYR, NT>(e.lat, q ? spare : main_copy, q ? main_copy : spare, e.lists, e.nbx, e.ntiles, e.kmax,
+                             q, b - e.block_begin);
 }
 
 namespace {
@@ -1393,6 +1458,28 @@ hipError_t launch_pipe_t(const LatDev &L, const uint8_t *src, uint8_t *dst, uint
         hipLaunchKernelGGL((k_sweep_i8_pipe<TXD, TYR, 512>), dim3(blocks), dim3(512), lds, s, L, src, dst, lists,
                            nbx, tiles, kmax, q);
     return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+hipError_t launch_pipe_batch_t(const PipeEntry *ents, const uint32_t *begins, uint32_t n_ents, uint32_t blocks,
+                               uint32_t Zmax, uint32_t nt, uint32_t g, hipStream_t s) {
+    const size_t lds = GeoP<TXD, TYR>::lds_bytes(Zmax);
+    if (nt == 1024)
+        hipLaunchKernelGGL((k_sweep_i8_pipe_batch<TXD, TYR, 1024>), dim3(blocks), dim3(1024), lds, s, ents, begins,
+                           n_ents, g);
+    else
+        hipLaunchKernelGGL((k_sweep_i8_pipe_batch<TXD, TYR, 512>), dim3(blocks), dim3(512), lds, s, ents, begins,
+                           n_ents, g);
+    return hipGetLastError();
+}
+
+template <int TXD, int TYR>
+uint32_t pipe_batch_static_lds_t(uint32_t nt) {
+    hipFuncAttributes a{};
+    const hipError_t e = nt == 1024
+                             ? hipFuncGetAttributes(&a, (const void *)k_sweep_i8_pipe_batch<TXD, TYR, 1024>)
+                             : hipFuncGetAttributes(&a, (const void *)k_sweep_i8_pipe_batch<TXD, TYR, 512>);
+    return e == hipSuccess ? (uint32_t)a.sharedSizeBytes : 0xFFFFFFFFu;
 }
 
 template <int TXD, int TYR>
@@ -1544,6 +1631,42 @@ uint32_t pipe_static_lds(uint32_t tx, uint32_t ty, uint32_t nt) {
     ISF_PIPE_SHAPES(ISF_CASE)
 #undef ISF_CASE
     return 0xFFFFFFFFu;
+}
+
+uint32_t pipe_batch_static_lds(uint32_t tx, uint32_t ty, uint32_t nt) {
+#define ISF_CASE(A, B) \
+    if (tx == A && ty == B) \
+        return pipe_batch_static_lds_t<A, B>(nt);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return 0xFFFFFFFFu;
+}
+
+// The block grid of a pipelined sweep of film L with at most `cap` blocks (more
+// if a block would get over kPipeTiles tiles): tiles along a row, tiles,
+// blocks, most tiles per block.  The film's lists must be built with the same cap.
+bool pipe_grid(const LatDev &L, uint32_t tx, uint32_t ty, uint32_t cap, uint32_t *nbx, uint32_t *tiles,
+               uint32_t *blocks, uint32_t *kmax) {
+#define ISF_CASE(A, B)                                                   \
+    if (tx == A && ty == B) {                                            \
+        pipe_grid_of<A, B>(L, cap, *nbx, *tiles, *blocks, *kmax);        \
+        return true;                                                     \
+    }
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return false;
+}
+
+// One batched pipelined sweep (index g) over every film of the table.
+hipError_t launch_sweep_i8_pipe_batch(const PipeEntry *ents, const uint32_t *begins, uint32_t n_ents,
+                                      uint32_t blocks, const Tiling &tl, uint32_t Zmax, uint32_t g, hipStream_t s) {
+    const uint32_t nt = 64u * tl.ry;
+#define ISF_CASE(A, B) \
+    if (tl.tx == A && tl.ty == B) \
+        return launch_pipe_batch_t<A, B>(ents, begins, n_ents, blocks, Zmax, nt, g, s);
+    ISF_PIPE_SHAPES(ISF_CASE)
+#undef ISF_CASE
+    return hipErrorInvalidValue;
 }
 
 uint32_t pipe_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z) {

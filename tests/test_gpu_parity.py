@@ -509,8 +509,7 @@ def test_pipe_kernel_rejects_unsupported(isf):
     for bad in ((32, 8, 16), (16, 16, 16), (32, 16, 4), (32, 16, 32)):
         with pytest.raises(IsfError):
             g.set_tuning(bad[0], bad[1], bad[2], False, 3)
-    for hh, Z in ((_rand_h((64, 328), 4, 2), 4),  # 41 dwords per row: not whole 16-byte pieces
-                  (_rand_h((64, 256), 4, 3), 4),  # narrower than one 32 x 16 region (40 dwords)
+    for hh, Z in ((_rand_h((64, 256), 4, 3), 4),  # narrower than one 32 x 16 region (40 dwords)
                   (_rand_h((16, 512), 4, 4), 4),  # lower than one region (24 rows)
                   (np.full((32, 512), 64, dtype=np.uint8), 64)):  # LDS of a 64-plane double buffer
         with pytest.raises(IsfError):
@@ -806,3 +805,48 @@ def test_draw_ceiling_checksum_equals_oracle_generator(isf, fmt):
                         want ^= w
     assert x == want and ms > 0
     np.testing.assert_array_equal(g.spins(), cpu.Film(h, Z, seed, rep).spins())  # the film is untouched
+
+
+# ------------------------------------------------------------------ pipelined kernel on any row width
+@pytest.mark.parametrize("X,Y,Z,tiling", [(328, 46, 6, (32, 32, 16)), (344, 48, 5, (32, 16, 16)),
+                                          (344, 48, 5, (32, 32, 8)), (488, 40, 8, (32, 32, 16))])
+def test_pipe_kernel_rows_not_whole_pieces(isf, X, Y, Z, tiling):
+    """Rows of 41, 43 and 61 dwords: a 16-byte piece would straddle the periodic seam, so
+    regions load dword by dword and whole tiles are written dword by dword (ragged tiles
+    in both directions, through reversal sweeps that overflow the change lists)."""
+    h = _rand_h((Y, X), Z, X + Y)
+    g, o = _pair(isf, h, Z, 0xABCDEF12, replica=4, init=2, tuning=tiling + (True, 3))
+    _say("pipe, odd rows", X, Y, Z, tiling)
+    steps = [(2.5, 60, 70, 0), (3.0, -80, 66, 3), (1.5, 100, 3, 1), (4.0, -20, 21, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*st).as_tuple() for st in steps]))
+    _assert_same(g, o)
+
+
+def test_batched_pipe_mode_equals_alone_and_oracle(isf):
+    """The batched pipelined mode: films it takes (rows of 40 dwords or more, 41 and 43 among
+    them, at least 40 rows, Z <= 8) share one launch per sweep; the others (too narrow, too
+    few rows, nine planes) run in the sublattice mode in the same call.  Schedules of
+    different lengths, so films sit out launches; advanced in chunks."""
+    rng = np.random.default_rng(321)
+    shapes = [(328, 46, 6), (344, 48, 8), (320, 56, 2), (512, 40, 3), (64, 40, 3), (336, 24, 4), (320, 48, 9)]
+    films = []
+    for i, (X, Y, Z) in enumerate(shapes):
+        h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+        T = float(rng.uniform(1.0, 9.0))
+        sched = [(T, int(hv), int(rng.integers(3, 30)), 0) for hv in rng.integers(-80, 81, size=2 + i % 3)]
+        films.append((h, Z, 700 + i, i, sched))
+    _say("batched pipe mode")
+    lats = [isf.Lattice(h, Z, s, replica=r, init=2) for (h, Z, s, r, sc) in films]
+    b = isf.Batch(len(lats))
+    for lat, f in zip(lats, films):
+        lat.schedule_load(f[4])
+    while sum(l.remaining() for l in lats):
+        b.advance(lats, 17, mode=3)
+    b.sync()
+    for (h, Z, s, r, sc), lat in zip(films, lats):
+        rec = lat.records()
+        o = cpu.Film(h, Z, s, r, init=2)
+        np.testing.assert_array_equal(rec, np.array([o.run(*st).as_tuple() for st in sc]), err_msg="film %d" % r)
+        np.testing.assert_array_equal(lat.spins(), o.spins(), err_msg="film %d" % r)
+        alone = isf.Lattice(h, Z, s, replica=r, init=2)
+        np.testing.assert_array_equal(alone.run_schedule(sc), rec, err_msg="film %d alone" % r)

@@ -15,8 +15,9 @@ host's cores.
       and bit-packed, equal record for record and spin for spin, and the
       oracle on 16 steps spread over the loop, the two field reversals among
       them;
-  batched: all 256 replicas on the first three steps, and the whole 201-step
-      ramp of the smallest, a median and the largest film in 16 segments;
+  batched: all 256 replicas on the first three steps (pipelined batch mode,
+      equal to the sublattice mode), and the whole 201-step ramp of the
+      smallest, a median and the largest film in 16 segments;
   serving: a stratified sample of the Poisson request stream (largest sides,
       one and ten layers, both job kinds) on shortened schedules in a mix:
       alone == in the mix for all of them, the oracle for those it finishes in
@@ -189,8 +190,16 @@ def test_batched_all_replicas_prefix_and_whole_ramps(isf):
     lats = [isf.Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
     b = isf.Batch(len(lats), stream=stream)
     _say("batched: %d replicas, %d-step prefix" % (len(reps), n_pre))
-    pre = b.run(lats, [[(r.T, hv, spst, 0) for hv in hnums[:n_pre]] for r in reps], mode=0)
+    pre = b.run(lats, [[(r.T, hv, spst, 0) for hv in hnums[:n_pre]] for r in reps], mode=3)
     pre_spins = [l.spins() for l in lats]
+    del lats, b
+    # the sublattice mode gives the same trajectories
+    lats = [isf.Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
+    b = isf.Batch(len(lats), stream=stream)
+    pre0 = b.run(lats, [[(r.T, hv, spst, 0) for hv in hnums[:n_pre]] for r in reps], mode=0)
+    for i, l in enumerate(lats):
+        np.testing.assert_array_equal(pre0[i], pre[i], err_msg="replica %d, modes 0 and 3" % reps[i].replica)
+        np.testing.assert_array_equal(l.spins(), pre_spins[i], err_msg="replica %d, modes 0 and 3" % reps[i].replica)
     del lats, b
 
     def prefix(i):
@@ -217,7 +226,7 @@ def test_batched_all_replicas_prefix_and_whole_ramps(isf):
     snaps = {p: [lats[p].spins()] for p in picks}
     recs = {p: [] for p in picks}
     for a, e in zip(bounds[:-1], bounds[1:]):
-        out = b.run(lats, [[(r.T, hv, spst, 0) for hv in hnums[a:e]] for r in reps], mode=0)
+        out = b.run(lats, [[(r.T, hv, spst, 0) for hv in hnums[a:e]] for r in reps], mode=3)
         for p in picks:
             recs[p].append(out[p])
             snaps[p].append(lats[p].spins())
