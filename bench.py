@@ -238,22 +238,28 @@ def bench_batched(args):
     import torch
 
     from isf_workloads import batched_films
-    from paper_1205_5588_amd.autotune import tune_batch
+    from paper_1205_5588_amd.autotune import lookup, tune_batch
     from paper_1205_5588_amd.lattice import Batch, Lattice
 
     reps, seed, hnums, spst = batched_films()
     stream = torch.cuda.Stream()
     sched = [[(r.T, hv, spst, 0) for hv in hnums] for r in reps]
 
-    def make():
-        return [Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream) for r in reps]
+    heights = {}
+    for r in reps:
+        if r.film not in heights:
+            heights[r.film] = r.heights()
+
+    def make(fmt=0):
+        return [Lattice(heights[r.film], r.Z, seed, replica=r.replica, init=0, fmt=fmt, stream=stream) for r in reps]
 
     t0 = time.perf_counter()
-    tuned = tune_batch(make, lambda i: sched[i], 0, sweeps=6)
-    log("batch tuning %.1fs: best %s mode %d (%.3f ms/sweep)" % (time.perf_counter() - t0, tuned["tiling"],
-                                                                 tuned["mode"], tuned["ms_per_sweep"]))
+    tuned = tune_batch(make, lambda i: sched[i], 0, sweeps=6, formats=(0, 1))
+    log("batch tuning %.1fs: best %s mode %d format %d (%.3f ms/sweep); skipped %s" % (
+        time.perf_counter() - t0, tuned["tiling"], tuned["mode"], tuned["format"], tuned["ms_per_sweep"],
+        tuned["skipped"]))
     kernel = KERNEL_SWEEP if tuned["mode"] == 2 else 0
-    lats = make()
+    lats = make(tuned["format"])
     for l in lats:
         l.set_tuning(*tuned["tiling"], False, kernel)
     n_occ = [l.observables()["n_occ"] for l in lats]
@@ -265,8 +271,10 @@ def bench_batched(args):
     attempts = sum(n * len(hnums) * spst for n in n_occ)
     out = {"value": round(attempts / dt, 1), "unit": "spin-flip attempts/s", "replicas": len(reps),
            "sweeps_per_replica": len(hnums) * spst, "attempts": attempts, "seconds": round(dt, 4),
-           "mode": {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[tuned["mode"]], "tiling": tuned["tiling"],
-           "tuning": tuned["all"]}
+           "mode": {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[tuned["mode"]],
+           "format": {0: "int8", 1: "bitpack"}[tuned["format"]], "tiling": tuned["tiling"],
+           "tuning": tuned["all"], "tuning_skipped": tuned["skipped"],
+           "graphs": "chunks of 64 sweeps replayed from a cached graph"}
     # the same replicas one after another through the plain path (a sample, shortened schedule)
     sample = list(range(0, len(reps), 16))
     short = 10
@@ -274,8 +282,8 @@ def bench_batched(args):
     att = 0
     for i in sample:
         r = reps[i]
-        l = Lattice(r.heights(), r.Z, seed, replica=r.replica, init=0, stream=stream)
-        l.set_tuning(*tuned["tiling"], True, kernel)
+        l = Lattice(heights[r.film], r.Z, seed, replica=r.replica, init=0, stream=stream)
+        l.set_tuning(*lookup(r.X, r.Y, r.Z, 0))  # the plain path's shape for this film
         torch.cuda.synchronize()
         ts = time.perf_counter()
         l.run_schedule(sched[i][:short])
@@ -284,7 +292,8 @@ def bench_batched(args):
         l.close()
     out["plain_same_replicas"] = {"value": round(att / max(plain_dt, 1e-9), 1),
                                   "sample": "16 replicas (one per film), first %d field steps, run one after "
-                                            "another through the plain path with graph replay" % short}
+                                            "another through the plain path (its own launch shape per film, "
+                                            "graph replay)" % short}
     del lats, b
     return out
 

@@ -12,6 +12,7 @@ Results are cached in JSON keyed by the film shape class.
 
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
@@ -150,45 +151,67 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
 
 # (tile_x, tile_y, rows or waves, batch mode); in the pipelined mode the shape is
 # that of the films the pipelined kernel cannot take (sublattice launches)
-BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH), (16, 16, 4, BATCH_WHOLE),
-                    (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE), (64, 4, 2, BATCH_PIPE),
-                    (32, 8, 2, BATCH_PIPE)]
+BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH), (64, 4, 2, BATCH_PERSISTENT),
+                    (16, 16, 4, BATCH_WHOLE), (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE),
+                    (64, 4, 2, BATCH_PIPE), (32, 8, 2, BATCH_PIPE)]
 
 
-def tune_batch(make_lats: Callable[[], list], schedule_of: Callable[[int], list], fmt: int,
-               sweeps: int = 8, candidates: Optional[Sequence[Tuple[int, int, int, int]]] = None) -> dict:
+def tune_batch(make_lats: Callable[..., list], schedule_of: Callable[[int], list], fmt: int,
+               sweeps: int = 8, candidates: Optional[Sequence[Tuple[int, int, int, int]]] = None,
+               formats: Optional[Sequence[int]] = None) -> dict:
     """Time (tile_x, tile_y, rows_or_waves, batch mode) candidates on a batch of films
-    (fresh copies per candidate); whole-sweep candidates apply to INT8 films only."""
+    (fresh copies per candidate, built by make_lats(fmt)), for each spin format in
+    `formats` (default: fmt alone).  Whole-sweep and pipelined modes apply to INT8
+    films only; a format the films cannot take (bit-packed rows need X % 64 == 0)
+    and a candidate the library refuses or that reports a failed run are skipped.
+    Every candidate must give every film the same records and spins."""
     import torch
 
     from .lattice import Batch
 
-    cands = [c for c in (candidates or BATCH_CANDIDATES) if fmt == FORMAT_INT8 or c[3] not in (BATCH_WHOLE, BATCH_PIPE)]
     timings = []
+    skipped = []
     ref = None
-    for tx, ty, r, mode in cands:
-        lats = make_lats()
-        kernel = KERNEL_SWEEP if mode == BATCH_WHOLE else KERNEL_TILES
-        for i, l in enumerate(lats):
-            l.set_tuning(tx, ty, r, False, kernel)
-            l.schedule_load(schedule_of(i))
-        b = Batch(len(lats))
-        b.advance(lats, 2, mode)  # warm-up sweeps
-        b.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.advance(lats, sweeps, mode)
-        b.sync()
-        dt = time.perf_counter() - t0
-        state = [l.observables() for l in lats]
-        key = [(s["M"], s["E"], s["sweeps"]) for s in state]
-        if ref is None:
-            ref = key
-        elif key != ref:
-            raise AssertionError("batch shape %s mode %d changed the trajectory" % ((tx, ty, r), mode))
-        timings.append({"tiling": [tx, ty, r], "mode": mode, "ms_per_sweep": dt * 1e3 / sweeps})
-        b.close()
-        for l in lats:
-            l.close()
+    for f in (formats or [fmt]):
+        cands = [c for c in (candidates or BATCH_CANDIDATES)
+                 if f == FORMAT_INT8 or c[3] not in (BATCH_WHOLE, BATCH_PIPE)]
+        for tx, ty, r, mode in cands:
+            try:
+                lats = make_lats(f)
+            except (IsfError, ValueError) as e:
+                skipped.append({"format": f, "reason": str(e)})
+                break
+            kernel = KERNEL_SWEEP if mode == BATCH_WHOLE else KERNEL_TILES
+            b = None
+            try:
+                for i, l in enumerate(lats):
+                    l.set_tuning(tx, ty, r, False, kernel)
+                    l.schedule_load(schedule_of(i))
+                b = Batch(len(lats))
+                b.advance(lats, 2, mode)  # warm-up sweeps
+                b.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                b.advance(lats, sweeps, mode)
+                b.sync()
+                dt = time.perf_counter() - t0
+            except IsfError as e:
+                skipped.append({"format": f, "tiling": [tx, ty, r], "mode": mode, "reason": str(e)})
+                for l in lats:
+                    l.close()
+                if b is not None:
+                    b.close()
+                continue
+            state = [(tuple(l.observables().values()), hashlib.sha256(l.spins().tobytes()).hexdigest()) for l in lats]
+            if ref is None:
+                ref = state
+            elif state != ref:
+                raise AssertionError("batch shape %s mode %d format %d changed a trajectory" % ((tx, ty, r), mode, f))
+            timings.append({"format": f, "tiling": [tx, ty, r], "mode": mode, "ms_per_sweep": dt * 1e3 / sweeps})
+            b.close()
+            for l in lats:
+                l.close()
+            del state
     best = min(timings, key=lambda r: r["ms_per_sweep"])
-    return {"tiling": best["tiling"], "mode": best["mode"], "ms_per_sweep": best["ms_per_sweep"], "all": timings}
+    return {"format": best["format"], "tiling": best["tiling"], "mode": best["mode"],
+            "ms_per_sweep": best["ms_per_sweep"], "all": timings, "skipped": skipped}

@@ -250,6 +250,12 @@ struct isf_batch {
     void *staging;         // pinned host: BatchEntry or WholeEntry records
     hipEvent_t staged;     // recorded after the last staging copy
     bool persistent_used;  // a persistent launch ran since the last check
+    // cached graphs of the launches of kBatchGraphSweeps sweeps, for the launch
+    // sequences graph_key names (mode, table size, blocks, shape, format,
+    // depth); two, since the pipelined mode also runs a sublattice sequence
+    hipGraphExec_t graph[2];
+    uint64_t graph_key[2][4];
+    uint32_t graph_next;  // the slot a new sequence replaces
 };
 
 namespace {
@@ -1483,6 +1489,9 @@ int32_t isf_batch_create(uint32_t max_lats, void *ws, uint64_t ws_bytes, void *s
 int32_t isf_batch_destroy(isf_batch *b) {
     if (!b)
         return fail(ISF_EINVAL, "null batch");
+    for (hipGraphExec_t g : b->graph)
+        if (g)
+            (void)hipGraphExecDestroy(g);
     (void)hipEventSynchronize(b->staged);
     (void)hipEventDestroy(b->staged);
     (void)hipHostFree(b->staging);
@@ -1507,6 +1516,65 @@ int32_t isf_batch_sync(isf_batch *b) {
 }  // extern "C"
 
 namespace {
+
+constexpr uint32_t kBatchGraphSweeps = 64;  // even: sweep parities alternate within a graph
+
+// Enqueue `sweeps` sweeps of a batch's per-sweep launch sequence `one(g)` (g:
+// the sweep's index in this call; launches that alternate with g & 1 need the
+// even graph length): replays of a cached graph of kBatchGraphSweeps sweeps
+// while that many remain, then plain launches.  The graph is captured again
+// when the sequence (key) changes; the launch table it reads is uploaded on
+// the stream before it, so a new table needs no new graph.
+template <class F>
+int32_t batch_enqueue(isf_batch *b, const uint64_t key[4], uint64_t sweeps, F one) {
+    uint64_t g = 0;
+    if (b->stream && sweeps >= kBatchGraphSweeps) {
+        uint32_t slot = 2;
+        for (uint32_t i = 0; i < 2; ++i)
+            if (b->graph[i] && std::memcmp(b->graph_key[i], key, sizeof b->graph_key[i]) == 0)
+                slot = i;
+        if (slot == 2) {
+            slot = b->graph_next;
+            b->graph_next ^= 1u;
+            if (b->graph[slot]) {
+                (void)hipGraphExecDestroy(b->graph[slot]);
+                b->graph[slot] = nullptr;
+            }
+            hipGraph_t gr = nullptr;
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            int32_t rc = ISF_OK;
+            for (uint32_t i = 0; i < kBatchGraphSweeps && rc == ISF_OK; ++i)
+                rc = one(i);
+            const hipError_t e = hipStreamEndCapture(b->stream, &gr);
+            if (rc) {
+                if (gr)
+                    (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return fail(ISF_EHIP, "batch graph capture: %s", hipGetErrorString(e));
+            const hipError_t ei = hipGraphInstantiate(&b->graph[slot], gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess) {
+                b->graph[slot] = nullptr;
+                return fail(ISF_EHIP, "batch graph instantiate: %s", hipGetErrorString(ei));
+            }
+            std::memcpy(b->graph_key[slot], key, sizeof b->graph_key[slot]);
+        }
+        for (; sweeps - g >= kBatchGraphSweeps; g += kBatchGraphSweeps)
+            HIP_TRY(hipGraphLaunch(b->graph[slot], b->stream));
+    }
+    for (; g < sweeps; ++g) {
+        int32_t rc = one((uint32_t)g);
+        if (rc)
+            return rc;
+    }
+    return ISF_OK;
+}
+
+uint64_t tiling_key(const Tiling &t) {
+    return (uint64_t)t.tx | ((uint64_t)t.ty << 16) | ((uint64_t)t.ry << 32) | ((uint64_t)t.kernel << 48);
+}
 
 // Batched whole-sweep mode: one launch per sweep over the tiles of every film.
 // The caller has waited for the staging area and records b->staged after.
@@ -1573,12 +1641,13 @@ int32_t batch_advance_whole(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
     HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(WholeEntry) * m, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->ws_dev + wl.begins, stage_begins, sizeof(uint32_t) * (m + 1), hipMemcpyHostToDevice,
                            b->stream));
-    for (uint64_t g = 0; g < sweeps; ++g) {
-        hipError_t e =
-            launch_sweep_i8_halo_batch(ents, begins, m, blocks, tl, Zmax, (uint32_t)(g & 1u), b->stream);
-        if (e != hipSuccess)
-            return fail(ISF_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
-    }
+    const uint64_t key[4] = {ISF_BATCH_WHOLE, ((uint64_t)m << 32) | blocks, tiling_key(tl), Zmax};
+    int32_t rc = batch_enqueue(b, key, sweeps, [&](uint32_t g) -> int32_t {
+        hipError_t e = launch_sweep_i8_halo_batch(ents, begins, m, blocks, tl, Zmax, g & 1u, b->stream);
+        return e == hipSuccess ? ISF_OK : fail(ISF_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
+    });
+    if (rc)
+        return rc;
     // a film past its schedule's end sits out the remaining launches: its spins
     // moved once per sweep it ran
     for (uint32_t i = 0; i < n; ++i) {
@@ -1636,7 +1705,8 @@ int32_t batch_advance_phase(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
     uint32_t *barrier = reinterpret_cast<uint32_t *>(b->ws_dev + wl.barrier);
     HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(BatchEntry) * m, hipMemcpyHostToDevice, b->stream));
     if (mode == ISF_BATCH_PHASE_LAUNCH) {
-        for (uint64_t sw = 0; sw < sweeps; ++sw) {
+        const uint64_t key[4] = {ISF_BATCH_PHASE_LAUNCH, ((uint64_t)m << 32) | blocks, tiling_key(tl), format};
+        int32_t rc = batch_enqueue(b, key, sweeps, [&](uint32_t) -> int32_t {
             for (uint32_t s = 0; s < 4; ++s) {
                 hipError_t e = format == ISF_FORMAT_INT8
                                    ? launch_phase_i8_batch(ents, m, blocks, tl, s, b->stream)
@@ -1645,9 +1715,10 @@ int32_t batch_advance_phase(isf_batch *b, isf_lattice *const *lats, uint32_t n, 
                     return fail(ISF_EHIP, "batched phase launch: %s", hipGetErrorString(e));
             }
             hipError_t e = launch_sweep_end_batch(ents, m, b->stream);
-            if (e != hipSuccess)
-                return fail(ISF_EHIP, "batched sweep-end launch: %s", hipGetErrorString(e));
-        }
+            return e == hipSuccess ? ISF_OK : fail(ISF_EHIP, "batched sweep-end launch: %s", hipGetErrorString(e));
+        });
+        if (rc)
+            return rc;
     } else {
         // chunks keep the barrier's arrival counter (sweeps x 5 x grid) far below 2^32
         for (uint64_t done = 0; done < sweeps;) {
@@ -1734,11 +1805,13 @@ int32_t batch_advance_pipe(isf_batch *b, isf_lattice *const *lats, uint32_t n, u
         HIP_TRY(hipMemcpyAsync(ents, stage, sizeof(PipeEntry) * m, hipMemcpyHostToDevice, b->stream));
         HIP_TRY(hipMemcpyAsync(b->ws_dev + wl.begins, stage_begins, sizeof(uint32_t) * (m + 1),
                                hipMemcpyHostToDevice, b->stream));
-        for (uint64_t g = 0; g < sweeps; ++g) {
-            hipError_t e = launch_sweep_i8_pipe_batch(ents, begins, m, blocks, tl, Zp, (uint32_t)(g & 1u), b->stream);
-            if (e != hipSuccess)
-                return fail(ISF_EHIP, "batched pipelined launch: %s", hipGetErrorString(e));
-        }
+        const uint64_t key[4] = {ISF_BATCH_PIPE, ((uint64_t)m << 32) | blocks, tiling_key(tl), Zp};
+        int32_t rc = batch_enqueue(b, key, sweeps, [&](uint32_t g) -> int32_t {
+            hipError_t e = launch_sweep_i8_pipe_batch(ents, begins, m, blocks, tl, Zp, g & 1u, b->stream);
+            return e == hipSuccess ? ISF_OK : fail(ISF_EHIP, "batched pipelined launch: %s", hipGetErrorString(e));
+        });
+        if (rc)
+            return rc;
         for (isf_lattice *lat : pipe) {
             const uint64_t ran = std::min<uint64_t>(lat->sched_total - lat->sched_enqueued, sweeps);
             if (ran & 1u)
