@@ -430,6 +430,9 @@ def main():
                     help="also run a plain device copy of this many MiB (calibrates rocprofv3 byte counters)")
     ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched"], default=None,
                     help="run only this one of the extra measurements and print its result (for profiling)")
+    ap.add_argument("--plain-tiling", default=None,
+                    help="the plain ramp's launch shape tx,ty,rows,kernel,graph instead of the tuner's (graph 0: "
+                         "plain launches, e.g. for counter passes that need no graph replay)")
     ap.add_argument("--tiling", default=None,
                     help="with --only bitpack or anisotropy: the launch shape tx,ty,rows[,kernel] "
                          "(kernel 0: tiles, 1: occupied-dword lists; no tuning)")
@@ -463,7 +466,13 @@ def main():
 
     tuning = lookup(cfg.X, cfg.Y, cfg.Z, 0)  # cached or heuristic shape, replaced by the tuner's pick
     tune_info = None
-    if not args.no_tune:
+    if args.plain_tiling:
+        v = [int(x) for x in args.plain_tiling.split(",")]
+        if len(v) != 5:
+            print("bench.py: --plain-tiling takes tx,ty,rows,kernel,graph", file=sys.stderr)
+            sys.exit(2)
+        tuning = (v[0], v[1], v[2], bool(v[4]), v[3])
+    elif not args.no_tune:
         t0 = time.perf_counter()
         tune_info = tune_plain(cfg, h, 0)
         tuning = tuple(tune_info["tiling"]) + (tune_info["use_graph"], tune_info["kernel"])
