@@ -50,7 +50,7 @@ def ramp_schedule(cfg, hs_num=0, an_num=0):
     return [(cfg.T, hv, cfg.sweeps_per_step, 0, hs_num, an_num) for hv in cfg.h_nums]
 
 
-def bench_ramp(cfg, h, fmt, k, warmup, tuning=None, hs_num=0, an_num=0):
+def bench_ramp(cfg, h, fmt, k, warmup, tuning=None, hs_num=0, an_num=0, aniso_ws=False):
     """The whole ramp on a fresh film, with k of its field steps timed.
 
     `warmup` untimed steps at the ramp's first field come first.  Then the
@@ -62,6 +62,8 @@ def bench_ramp(cfg, h, fmt, k, warmup, tuning=None, hs_num=0, an_num=0):
     from paper_1205_5588_amd.lattice import Lattice
 
     lat = Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init, fmt=fmt)
+    if aniso_ws:
+        lat.attach_aniso_workspace()
     if tuning:
         if len(tuning) > 4 and tuning[4] == 1:
             lat.attach_items()
@@ -407,9 +409,26 @@ def run_only(args, cfg, h):
             kern = tb["kernel"]
         tuning = None if tl is None else tl + (True, kern)
         return bitpack_fields(bench_ramp(cfg, h, 1, args.steps, 2, tuning), cfg)
-    tl = tl or (64, 4, 2)
-    r = bench_ramp(cfg, h, 0, args.steps, 2, tl + (True, kern), an_num=40)
-    return {**ramp_summary(r, cfg), "an_num": 40, "tiling": list(tl), "kernel": kern}
+    if tl is None:
+        tl, kern = (32, 32, 16), KERNEL_PIPE
+    return bench_aniso(cfg, h, args.steps, tl + (True, kern))
+
+
+def bench_aniso(cfg, h, k, tuning):
+    """The ramp with the anisotropy term of Eq. 7, h_an = 2 (an_num = 40).  On a whole-sweep
+    kernel each field step runs at field h + h_an sign(M) from a copy of the spins and state,
+    and again on the per-sublattice kernels (M frozen per phase) where the accepted flips do not
+    rule out |M| < 2 at a phase start; on the per-sublattice kernels the term is applied phase
+    by phase throughout."""
+    whole = tuning[4] in (KERNEL_SWEEP, KERNEL_PIPE)
+    r = bench_ramp(cfg, h, 0, k, 2, tuning, an_num=40, aniso_ws=whole)
+    out = {**ramp_summary(r, cfg), "an_num": 40, "tiling": list(tuning[:3]),
+           "kernel": {KERNEL_SWEEP: "k_sweep_i8_halo", KERNEL_PIPE: "k_sweep_i8_pipe"}.get(tuning[4], "k_phase_i8")}
+    if whole:
+        runs, redone = r["lat"].aniso_stats()
+        out["step_parts_on_whole_kernel"] = runs
+        out["run_again_per_sublattice"] = redone
+    return out
 
 
 def main():
@@ -511,13 +530,13 @@ def main():
         log("gated:", extra["gated"])
         del rg
         # the same ramp with the anisotropy term of Eq. 7, h_an = 2 (an_num = 40), on the
-        # per-sublattice kernels (M frozen per phase)
-        an_tl = (64, 4, 2, True, 0)
-        ra = bench_ramp(cfg, h, 0, args.steps, 2, an_tl, an_num=40)
-        extra["anisotropy"] = {**ramp_summary(ra, cfg), "an_num": 40, "tiling": list(an_tl[:3]),
-                               "kernel": "k_phase_i8"}
+        # pipelined kernel (steps checked, and run again per sublattice near M = 0) and,
+        # for comparison, on the per-sublattice kernels alone (M frozen per phase)
+        extra["anisotropy"] = bench_aniso(cfg, h, args.steps, (32, 32, 16, True, KERNEL_PIPE))
+        extra["anisotropy"]["per_sublattice_kernels"] = {
+            k: v for k, v in bench_aniso(cfg, h, args.steps, (64, 4, 2, True, 0)).items()
+            if k in ("value", "ms_per_sweep", "whole_ramp", "kernel")}
         log("anisotropy:", extra["anisotropy"])
-        del ra
         extra["batched"] = bench_batched(args)
         log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
         if not args.no_serve:

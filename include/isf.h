@@ -107,10 +107,12 @@ typedef struct {
                            h_an = an_num / 20, 0 <= an_num <= 200000; 0: no anisotropy.  M couples every
                            site, so it is frozen at its value when each sublattice phase starts: a flip of
                            spin S changes q by -an_num (|M - 2S| - |M|) / 2 with that M (an extra field
-                           h_an sign(M) while |M| >= 2).  INT8 films on the per-sublattice kernels
-                           (ISF_KERNEL_TILES or _LIST) of a single lattice: isf_schedule_load returns
-                           EINVAL for a bit-packed film or a whole-sweep tuning, and isf_batch_advance
-                           refuses a lattice whose loaded schedule has it */
+                           h_an sign(M) while |M| >= 2).  INT8 films of a single lattice, on the
+                           per-sublattice kernels (ISF_KERNEL_TILES or _LIST), or on the whole-sweep
+                           kernels with a workspace attached (isf_attach_aniso_workspace):
+                           isf_schedule_load returns EINVAL for a bit-packed film or a whole-sweep tuning
+                           without a workspace, and isf_batch_advance refuses a lattice whose loaded
+                           schedule has it */
 } isf_step;
 
 typedef struct {
@@ -239,6 +241,35 @@ int32_t isf_film_stats(const isf_lattice *lat, isf_stats *out);
  * do not fit the 32-bit item encoding, ESTATE for BITPACK. */
 int32_t isf_items_bytes(const isf_lattice *lat, uint64_t *bytes);
 int32_t isf_attach_items(isf_lattice *lat, void *items_dev, uint64_t bytes);
+
+/* The anisotropy term of Eq. 7 on the whole-sweep kernels (INT8).  The term
+ * couples every site to M, frozen at each sublattice phase's start, and the
+ * whole-sweep kernels have no film-wide phase start.  But while |M| >= 2 at a
+ * phase start, the term is exactly an extra field h_an sign(M) (isf_step.an_num),
+ * so a run of sweeps in which M stays at |M| >= 2 with one sign is a plain run
+ * at field h_num + an_num sign(M).  With a workspace attached, isf_advance runs
+ * each step of an anisotropic schedule (or its part within one call) that way:
+ * it keeps a copy of the spins, the state and the step's record, runs the
+ * sweeps on the whole-sweep kernel at field h_num + an_num sign(M0) (M0 the
+ * magnetisation where they start), and keeps the result when every one of
+ * those sweeps had |M_s| - 2 a_s >= 2, M_s its starting magnetisation and a_s
+ * its flips (each flip moves M by 2, so no phase start came below |M| = 2 or
+ * changed sign).  Otherwise, or when |M0| < 2, the copy is restored and the
+ * sweeps run on the per-sublattice kernels (64 x 4 x 2 tiles).  The trajectory
+ * is that of the per-sublattice kernels either way.  Such an isf_advance
+ * synchronises the lattice's stream once or twice per step.
+ * isf_aniso_workspace_bytes gives the workspace size (the spin buffer, the
+ * state, one record and two threshold tables for each of up to ISF_MAX_STEPS
+ * steps, rounded up); the caller allocates that much device
+ * memory, 256-byte aligned, keeps it alive with the lattice and attaches it
+ * with isf_attach_aniso_workspace.  Without a workspace, a whole-sweep tuning
+ * and an anisotropic schedule exclude each other (EINVAL).  isf_aniso_stats
+ * counts the step parts run on the whole-sweep kernel since the workspace was
+ * attached and those of them run again.  EINVAL for a BITPACK film, a null or
+ * misaligned buffer; ENOSPC for a short buffer. */
+int32_t isf_aniso_workspace_bytes(const isf_lattice *lat, uint64_t *bytes);
+int32_t isf_attach_aniso_workspace(isf_lattice *lat, void *dev, uint64_t bytes);
+int32_t isf_aniso_stats(const isf_lattice *lat, uint64_t *speculated, uint64_t *redone);
 
 /* Choose the launch shape for a lattice (validated; EINVAL if unsupported). */
 int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *tuning);

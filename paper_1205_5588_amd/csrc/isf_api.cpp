@@ -240,6 +240,18 @@ struct isf_lattice {
     // the loaded schedule has the anisotropy term (also in L.aniso, which the
     // phase kernels read)
     bool aniso;
+    // the anisotropy term on the whole-sweep kernels: the caller's workspace
+    // (a copy of the spins, the state and a record, taken before each step),
+    // the loaded anisotropic schedule on the host, the host's copy of the
+    // schedule position (step, sweeps of it enqueued), and M and the step's
+    // accepted count at that position when a synchronisation has read them
+    uint8_t *spec_ws;
+    uint64_t spec_bytes;
+    std::vector<isf_step> spec_steps;
+    uint32_t spec_step, spec_sis;
+    bool spec_known;
+    int64_t spec_M;
+    uint64_t spec_runs, spec_redone;
 };
 
 struct isf_batch {
@@ -520,6 +532,187 @@ int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     return enqueue_sweeps_plain(lat, n);
 }
 
+// ---------------------------------------------------------------------------
+// The anisotropy term of Eq. (7) on the whole-sweep kernels.  While |M| >= 2 at
+// every sublattice phase start, a flip of spin s changes q by an s sign(M), so
+// the sweeps are plain sweeps at field h_num + an_num sign(M).  Each step (or its
+// part within one advance) is run that way from a copy of the spins, the state
+// and the step's record, and kept when every sweep of it had |M0| - 2 a >= 2
+// (M0 its starting magnetisation, a its flips: every flip moves M by 2, so no
+// phase start within the sweep, and not the next sweep's start, came below 2 or
+// changed sign); the books keep the minimum of that margin in the device state.
+// Otherwise the copy is restored and the sweeps run on the per-sublattice
+// kernels, which apply the term phase by phase.
+
+// Workspace layout: the spin buffer, the state, one record, and per step of
+// the schedule the tables of fields h_num + an_num and h_num - an_num.
+struct SpecLayout {
+    uint64_t state, record, tables, total;
+};
+
+SpecLayout spec_layout(const isf_desc &d) {
+    auto up = [](uint64_t v) { return (v + 255) / 256 * 256; };
+    SpecLayout l;
+    l.state = up(spin_bytes_of(&d));
+    l.record = l.state + up(sizeof(DevState));
+    l.tables = l.record + up(sizeof(isf_record));
+    l.total = l.tables + up(sizeof(uint32_t) * 2 * kTableWords * ISF_MAX_STEPS);
+    return l;
+}
+
+uint32_t *spec_tables(const isf_lattice *lat, uint32_t step, int32_t sgn) {
+    return reinterpret_cast<uint32_t *>(lat->spec_ws + spec_layout(lat->d).tables) +
+           ((size_t)step * 2 + (sgn > 0 ? 0 : 1)) * kTableWords;
+}
+
+// Upload the tables of fields h_num +- an_num of every step of the loaded
+// anisotropic schedule (synchronous).
+int32_t spec_upload(isf_lattice *lat) {
+    const size_t n = lat->spec_steps.size();
+    if (!lat->spec_ws || n == 0)
+        return ISF_OK;
+    std::vector<uint32_t> t(n * 2 * kTableWords);
+    for (size_t i = 0; i < n; ++i) {
+        const isf_step &st = lat->spec_steps[i];
+        table_of(st.T, st.h_num + st.an_num, st.hs_num, &t[(2 * i) * kTableWords]);
+        table_of(st.T, st.h_num - st.an_num, st.hs_num, &t[(2 * i + 1) * kTableWords]);
+    }
+    HIP_TRY(hipMemcpyAsync(spec_tables(lat, 0, 1), t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return ISF_OK;
+}
+
+const Tiling kSpecFallback{64, 4, 2, ISF_KERNEL_TILES};
+
+// The host's copy of the schedule position after n more sweeps.
+void spec_advance_pos(isf_lattice *lat, uint64_t n) {
+    while (n > 0 && lat->spec_step < lat->spec_steps.size()) {
+        const uint32_t len = lat->spec_steps[lat->spec_step].n_sweeps;
+        const uint64_t k = std::min<uint64_t>(n, len - lat->spec_sis);
+        lat->spec_sis += (uint32_t)k;
+        n -= k;
+        if (lat->spec_sis == len) {
+            ++lat->spec_step;
+            lat->spec_sis = 0;
+        }
+    }
+}
+
+// M and the current step's accepted count, read from the device state.
+int32_t spec_read(isf_lattice *lat, DevState *head) {
+    int32_t rc = flush_whole(lat);
+    if (rc)
+        return rc;
+    HIP_TRY(hipMemcpyAsync(head, lat->L.st, sizeof(DevState), hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    lat->spec_M = head->M;
+    lat->spec_known = true;
+    return ISF_OK;
+}
+
+// The current step's thresholds into the device state, for the next run to
+// start from: sgn = +1 / -1 the table of field h_num + / - an_num (workspace),
+// 0 the step's own table and its anisotropy halves.
+int32_t spec_set_tables(isf_lattice *lat, int32_t sgn) {
+    uint8_t *cur = lat->aux_dev + offsetof(DevState, cur_table);
+    const uint32_t s = lat->spec_step;
+    if (sgn) {
+        HIP_TRY(hipMemcpyAsync(cur, spec_tables(lat, s, sgn), sizeof(uint32_t) * kTableWords,
+                               hipMemcpyDeviceToDevice, lat->stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(cur, lat->L.tables + (size_t)s * kTableWords, sizeof(uint32_t) * kTableWords,
+                               hipMemcpyDeviceToDevice, lat->stream));
+        HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, cur_atable), lat->L.atables + (size_t)s * kAnWords,
+                               sizeof(uint32_t) * kAnWords, hipMemcpyDeviceToDevice, lat->stream));
+    }
+    return ISF_OK;
+}
+
+// k sweeps on the per-sublattice kernels, the term applied phase by phase.
+int32_t spec_fallback(isf_lattice *lat, uint64_t k) {
+    int32_t rc;
+    if ((rc = settle(lat)) || (rc = spec_set_tables(lat, 0)))
+        return rc;
+    const Tiling keep = lat->tiling;
+    lat->tiling = kSpecFallback;
+    rc = enqueue_sweeps_plain(lat, k);
+    lat->tiling = keep;
+    lat->spec_known = false;
+    return rc;
+}
+
+// k sweeps of the current step on the whole-sweep kernel, with the table of
+// field h_num + sgn an_num (sgn = 0: the step's own).
+int32_t spec_whole(isf_lattice *lat, int32_t sgn, uint64_t k) {
+    int32_t rc;
+    if ((rc = flush_whole(lat)) || (rc = spec_set_tables(lat, sgn)) || (rc = enqueue_sweeps(lat, k)))
+        return rc;
+    return flush_whole(lat);
+}
+
+// k sweeps of the current step with the anisotropy term, from |M0| >= 2.
+int32_t spec_try(isf_lattice *lat, uint64_t k) {
+    static const int64_t kNoMargin = INT64_MAX;
+    const int64_t M0 = lat->spec_M;
+    int32_t rc;
+    if ((rc = flush_whole(lat)))
+        return rc;
+    const SpecLayout sl = spec_layout(lat->d);
+    const bool was_spare = lat->cur_spare;
+    uint8_t *cur = was_spare ? lat->spare : lat->L.spins;
+    isf_record *rec = lat->L.records + lat->spec_step;
+    HIP_TRY(hipMemcpyAsync(lat->spec_ws, cur, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice, lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->spec_ws + sl.state, lat->L.st, sizeof(DevState), hipMemcpyDeviceToDevice,
+                           lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->spec_ws + sl.record, rec, sizeof(isf_record), hipMemcpyDeviceToDevice, lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->aux_dev + offsetof(DevState, spec_margin), &kNoMargin, sizeof kNoMargin,
+                           hipMemcpyHostToDevice, lat->stream));
+    if ((rc = spec_whole(lat, M0 > 0 ? 1 : -1, k)))
+        return rc;
+    DevState head;
+    if ((rc = spec_read(lat, &head)))
+        return rc;
+    ++lat->spec_runs;
+    if (head.spec_margin >= 2)
+        return ISF_OK;
+    // |M| may have come below 2 at some phase start: start again from the copy
+    ++lat->spec_redone;
+    uint8_t *back = was_spare ? lat->spare : lat->L.spins;
+    HIP_TRY(hipMemcpyAsync(back, lat->spec_ws, spin_bytes_of(&lat->d), hipMemcpyDeviceToDevice, lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->L.st, lat->spec_ws + sl.state, sizeof(DevState), hipMemcpyDeviceToDevice,
+                           lat->stream));
+    HIP_TRY(hipMemcpyAsync(rec, lat->spec_ws + sl.record, sizeof(isf_record), hipMemcpyDeviceToDevice, lat->stream));
+    lat->cur_spare = was_spare;
+    lat->spec_M = M0;
+    return spec_fallback(lat, k);
+}
+
+// n sweeps of an anisotropic schedule with a whole-sweep tuning, step by step.
+int32_t spec_advance(isf_lattice *lat, uint64_t n) {
+    while (n > 0) {
+        if (lat->spec_step >= lat->spec_steps.size())
+            return fail(ISF_ESTATE, "schedule position beyond the loaded schedule");
+        const isf_step &st = lat->spec_steps[lat->spec_step];
+        const uint64_t k = std::min<uint64_t>(n, st.n_sweeps - lat->spec_sis);
+        int32_t rc;
+        if (st.an_num == 0) {
+            rc = spec_whole(lat, 0, k);
+            lat->spec_known = false;
+        } else {
+            DevState head;
+            if (!lat->spec_known && (rc = spec_read(lat, &head)))
+                return rc;
+            rc = (lat->spec_M >= -1 && lat->spec_M <= 1) ? spec_fallback(lat, k) : spec_try(lat, k);
+        }
+        if (rc)
+            return rc;
+        spec_advance_pos(lat, k);
+        n -= k;
+    }
+    return ISF_OK;
+}
+
 // Compact start layout: vacancies 1, occupied sites 0 (INT8) or occupancy bits (BITPACK).
 void build_layout(const isf_desc &d, const uint8_t *h, std::vector<uint8_t> &buf) {
     const uint32_t X = d.X, Y = d.Y, Z = d.Z, W = X / 2;
@@ -739,6 +932,52 @@ int32_t isf_lattice_destroy(isf_lattice *lat) {
     return ISF_OK;
 }
 
+int32_t isf_aniso_workspace_bytes(const isf_lattice *lat, uint64_t *bytes) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(ISF_EINVAL, "null output");
+    if (lat->d.format != ISF_FORMAT_INT8)
+        return fail(ISF_EINVAL, "the anisotropy term needs an INT8 film");
+    *bytes = spec_layout(lat->d).total;
+    return ISF_OK;
+}
+
+int32_t isf_attach_aniso_workspace(isf_lattice *lat, void *dev, uint64_t bytes) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (lat->d.format != ISF_FORMAT_INT8)
+        return fail(ISF_EINVAL, "the anisotropy term needs an INT8 film");
+    if (!dev)
+        return fail(ISF_EINVAL, "null workspace");
+    if ((uintptr_t)dev & 255)
+        return fail(ISF_EINVAL, "workspace must be 256-byte aligned");
+    const uint64_t need = spec_layout(lat->d).total;
+    if (bytes < need)
+        return fail(ISF_ENOSPC, "workspace of %llu bytes < %llu", (unsigned long long)bytes,
+                    (unsigned long long)need);
+    if ((rc = set_device_of(lat)))
+        return rc;
+    lat->spec_ws = static_cast<uint8_t *>(dev);
+    lat->spec_bytes = bytes;
+    lat->spec_runs = 0;
+    lat->spec_redone = 0;
+    return spec_upload(lat);  // the loaded schedule's tables, if it has the term
+}
+
+int32_t isf_aniso_stats(const isf_lattice *lat, uint64_t *speculated, uint64_t *redone) {
+    int32_t rc = check_lat(lat);
+    if (rc)
+        return rc;
+    if (!speculated || !redone)
+        return fail(ISF_EINVAL, "null output");
+    *speculated = lat->spec_runs;
+    *redone = lat->spec_redone;
+    return ISF_OK;
+}
+
 int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
     int32_t rc = check_lat(lat);
     if (rc)
@@ -775,8 +1014,10 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
         if (!ok)
             return fail(ISF_EINVAL, "unsupported tiling %ux%ux%u", tl.tx, tl.ty, tl.ry);
     }
-    if (lat->aniso && is_whole(tl.kernel))
-        return fail(ISF_EINVAL, "the loaded schedule has the anisotropy term, which needs the per-sublattice kernels");
+    if (lat->aniso && is_whole(tl.kernel) && !lat->spec_ws)
+        return fail(ISF_EINVAL,
+                    "the loaded schedule has the anisotropy term, which needs the per-sublattice kernels or a "
+                    "workspace for the whole-sweep kernels (isf_attach_aniso_workspace)");
     lat->tiling = tl;
     lat->use_graph = t->use_graph != 0;
     return ISF_OK;
@@ -912,10 +1153,11 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
         if (steps[i].an_num != 0) {
             if (lat->d.format != ISF_FORMAT_INT8)
                 return fail(ISF_EINVAL, "step %u: the anisotropy term needs an INT8 film", i);
-            if (is_whole(lat->tiling.kernel))
+            if (is_whole(lat->tiling.kernel) && !lat->spec_ws)
                 return fail(ISF_EINVAL,
                             "step %u: the anisotropy term needs the per-sublattice kernels (tuning kernel TILES "
-                            "or LIST)", i);
+                            "or LIST), or a workspace for the whole-sweep kernels (isf_attach_aniso_workspace)",
+                            i);
             aniso = true;
         }
         table_of(steps[i].T, steps[i].h_num, steps[i].hs_num, &tabs[(size_t)i * kTableWords]);
@@ -953,6 +1195,15 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
         drop_graph(lat);  // a cached graph holds the launches' copy of L.aniso
     lat->aniso = aniso;
     lat->L.aniso = aniso ? 1u : 0u;
+    if (aniso)
+        lat->spec_steps.assign(steps, steps + n);
+    else
+        lat->spec_steps.clear();
+    lat->spec_step = 0;
+    lat->spec_sis = 0;
+    lat->spec_known = false;
+    if ((rc = spec_upload(lat)))
+        return rc;
     lat->sched_steps = n;
     lat->sched_total = total;
     lat->sched_enqueued = 0;
@@ -976,8 +1227,17 @@ int32_t isf_advance(isf_lattice *lat, uint32_t max_sweeps, uint64_t *enqueued) {
     if ((rc = set_device_of(lat)))
         return rc;
     const uint64_t n = std::min<uint64_t>(max_sweeps, lat->sched_total - lat->sched_enqueued);
-    if ((rc = enqueue_sweeps(lat, n)))
-        return rc;
+    if (lat->aniso && is_whole(lat->tiling.kernel)) {
+        if ((rc = prepare_spare(lat, lat->tiling)) || (rc = spec_advance(lat, n)))
+            return rc;
+    } else {
+        if ((rc = enqueue_sweeps(lat, n)))
+            return rc;
+        if (lat->aniso) {  // keep the host's copy of the position for a later whole-sweep tuning
+            spec_advance_pos(lat, n);
+            lat->spec_known = false;
+        }
+    }
     lat->sched_enqueued += n;
     if (enqueued)
         *enqueued = n;
@@ -1193,6 +1453,8 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         return fail(ISF_EINVAL, "null output");
     if ((rc = set_device_of(lat)))
         return rc;
+    if (lat->aniso && is_whole(lat->tiling.kernel))
+        return fail(ISF_EINVAL, "launch timing of an anisotropic schedule on a whole-sweep kernel is not supported");
     const uint32_t n = (uint32_t)std::min<uint64_t>(n_sweeps, lat->sched_total - lat->sched_enqueued);
     // timing-only events: no system-scope fence when they are recorded, so that
     // the pairs measure the launch between them and not a cache write-back

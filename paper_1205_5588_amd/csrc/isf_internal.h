@@ -52,6 +52,10 @@ struct alignas(256) DevState {
     int64_t recount[4];     // scratch of the full recount (M, sum s n, sites, occupied pairs)
     uint32_t cur_table[kTableWords];  // thresholds of the current step
     uint32_t cur_atable[kAnWords];    // its anisotropy thresholds (q + an, q - an), if the schedule has the term
+    // min over the sweeps the whole-sweep kernels folded since the host last set
+    // it of |M at the sweep's start| - 2 (flips in the sweep): while it is >= 2,
+    // every sublattice phase of those sweeps started at |M| >= 2 with M's sign
+    int64_t spec_margin;
 };
 
 // Per-sweep partial sums, one 128-byte line each so that atomics spread.

@@ -174,9 +174,12 @@ __device__ __forceinline__ void book_fold(const LatDev &L, uint32_t prev, const 
     const uint32_t p_pending = bk.w[7];
     if (lane == 0 && p_pending) {
         DevState *st = L.st;
-        const int64_t M = w64(bk, 16) + dM, E = w64(bk, 18) + dE;
+        const int64_t M0 = w64(bk, 16), M = M0 + dM, E = w64(bk, 18) + dE;
         st->M = M;
         st->E = E;
+        const int64_t margin = (M0 < 0 ? -M0 : M0) - 2 * acc;
+        if (margin < st->spec_margin)
+            st->spec_margin = margin;
         if (p_run) {
             int64_t sM = w64(bk, 24), sA = w64(bk, 26), sE = w64(bk, 28), sC = w64(bk, 30);
             if (p_sis >= p_nd) {
@@ -1006,7 +1009,9 @@ __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const ui
 // All dwords of phase S listed in ls[0 .. n), one per thread and iteration;
 // q0: the thread's first entry, read when the tile started.  The next entry is
 // read before the current attempt, so the few waves that take a second entry
-// at the end of the phase do not wait for it.
+// at the end of the phase do not wait for it.  Every lane reads one (the last
+// entry where it has none): a read under a lane mask made the compiler wait
+// for it at once, one more LDS round trip per entry.
 template <int S, int RX, int PL, int NT>
 __device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint32_t q0, uint32_t *Rb,
                                            const uint32_t *rowk, const uint32_t *dmap, const uint32_t *tab64,
@@ -1014,7 +1019,7 @@ __device__ __forceinline__ void pipe_phase(const uint16_t *ls, uint32_t n, uint3
                                            uint16_t *chg, uint32_t *chg_n, int &dM, int &dE, int &acc) {
     uint32_t i = threadIdx.x, q = q0;
     while (i < n) {
-        const uint32_t nxt = i + NT < n ? (uint32_t)ls[i + NT] : 0u;
+        const uint32_t nxt = ls[min(i + NT, n - 1u)];
         pipe_attempt<S, RX, PL>(q, Rb, rowk, dmap, tab64, gthr, t, psh, L, chg, chg_n, dM, dE, acc);
         q = nxt;
         i += NT;

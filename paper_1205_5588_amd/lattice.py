@@ -109,6 +109,23 @@ class Lattice:
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         check(_lib.load().isf_attach_items(self.handle, self.items_buf.data_ptr(), int(nb.value)))
 
+    def attach_aniso_workspace(self) -> None:
+        """Device workspace that lets the whole-sweep kernels run schedules with the
+        anisotropy term of Eq. 7 (steps run at field h + h_an sign(M) while |M| >= 2
+        is certain, otherwise again on the per-sublattice kernels)."""
+        torch = _torch()
+        nb = ctypes.c_uint64()
+        check(_lib.load().isf_aniso_workspace_bytes(self.handle, ctypes.byref(nb)))
+        self.aniso_ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(_lib.load().isf_attach_aniso_workspace(self.handle, self.aniso_ws.data_ptr(), int(nb.value)))
+
+    def aniso_stats(self) -> Tuple[int, int]:
+        """(step parts run on the whole-sweep kernel, those of them run again per sublattice)."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        check(_lib.load().isf_aniso_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     # ------------------------------------------------------------------ lifecycle
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -752,6 +752,65 @@ def test_aniso_large_film_prefix(isf):
     _assert_same(g, o)
 
 
+@pytest.mark.parametrize("kernel,tiling", [(3, (32, 16, 16)), (3, (32, 32, 16)), (2, (16, 16, 4)), (2, (32, 8, 4))])
+@pytest.mark.parametrize("X,Y,Z", [(328, 46, 6), (352, 48, 4)])
+def test_aniso_whole_kernels_match_oracle(isf, kernel, tiling, X, Y, Z):
+    """The term on the whole-sweep kernels (steps at field h + h_an sign(M), checked and run
+    again per sublattice where |M| could have come below 2): the schedule with discarded
+    sweeps, gated steps, T -> 0 and a step without the term, then the same again in
+    advances of 5 sweeps (steps cut in parts)."""
+    h = _rand_h((Y, X), Z, 7 * X + Y + Z)
+    g, o = _pair(isf, h, Z, 24680, replica=5, init=2)
+    g.attach_aniso_workspace()
+    g.set_tuning(tiling[0], tiling[1], tiling[2], True, kernel)
+    _say("aniso whole kernels", kernel, tiling, X, Y, Z)
+    np.testing.assert_array_equal(g.run_schedule(ANISO_STEPS), np.array([o.run(*s).as_tuple() for s in ANISO_STEPS]))
+    _assert_same(g, o)
+    g.schedule_load(ANISO_STEPS)
+    while g.advance(5):
+        pass
+    want = np.array([o.run(*s).as_tuple() for s in ANISO_STEPS])
+    np.testing.assert_array_equal(g.records(), want)
+    _assert_same(g, o)
+    runs, redone = g.aniso_stats()
+    assert runs > 0 and redone <= runs
+
+
+def test_aniso_whole_kernel_through_reversal(isf):
+    """A field ramp through M = 0 with the term: the speculative whole-sweep steps and the steps
+    run again per sublattice together equal the oracle and the per-sublattice kernels."""
+    X, Y, Z = 352, 48, 4
+    h = _rand_h((Y, X), Z, 31)
+    steps = [(3.0, hn, 20, 0, 0, 40) for hn in list(range(60, -121, -20)) + list(range(-100, 61, 20))]
+    g, o = _pair(isf, h, Z, 97531, replica=1, init=0)
+    g.attach_aniso_workspace()
+    g.set_tuning(32, 16, 16, True, 3)
+    _say("aniso whole kernel through the reversal")
+    rg = g.run_schedule(steps)
+    np.testing.assert_array_equal(rg, np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+    runs, redone = g.aniso_stats()
+    assert 0 < redone < runs, (runs, redone)
+    p = isf.Lattice(h, Z, 97531, replica=1, init=0)
+    p.set_tuning(64, 4, 2, True, 0)
+    np.testing.assert_array_equal(p.run_schedule(steps), rg)
+    np.testing.assert_array_equal(p.spins(), g.spins())
+
+
+def test_aniso_whole_kernel_large_film_prefix(isf):
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
+    g.attach_aniso_workspace()
+    g.set_tuning(32, 32, 16, True, 3)
+    _say("aniso whole kernel, large film prefix")
+    steps = [(c.T, hn, 3, 0, 0, 40) for hn in (120, 0, -60)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
 def test_aniso_rejected_where_unsupported(isf):
     from paper_1205_5588_amd._lib import IsfError
 
@@ -780,6 +839,11 @@ def test_aniso_rejected_where_unsupported(isf):
     g.set_tuning(32, 16, 16, True, 3)
     assert g.advance(2) == 2
     o.run(2.0, 10, 2)
+    # with a workspace the whole-sweep kernels take the term too
+    g.attach_aniso_workspace()
+    g.schedule_load([(2.0, 0, 3, 0, 0, 40)])
+    assert g.advance(3) == 3
+    o.run(2.0, 0, 3, 0, 0, 40)
     _assert_same(g, o)
 
 

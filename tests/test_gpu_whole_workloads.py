@@ -14,7 +14,8 @@ host's cores.
   large ramp 2048 x 2048 x 8: all 481 field steps in int8 (pipelined kernel)
       and bit-packed, equal record for record and spin for spin, and the
       oracle on 16 steps spread over the loop, the two field reversals among
-      them;
+      them; the same ramp with the anisotropy term on the pipelined kernel
+      equal to the per-sublattice kernels;
   batched: all 256 replicas on the first three steps (pipelined batch mode,
       equal to the sublattice mode), and the whole 201-step ramp of the
       smallest, a median and the largest film in 16 segments;
@@ -178,6 +179,36 @@ def test_large_ramp_whole_int8_bitpack_and_oracle(isf):
 
 
 # ------------------------------------------------------------------ batched
+@pytest.mark.timeout(900)
+def test_large_ramp_anisotropy_whole_kernel_equals_phase_kernels(isf):
+    """The large ramp with the anisotropy term of Eq. 7 (h_an = 2), all 481 steps: on the
+    pipelined whole-sweep kernel (steps at field h + h_an sign(M), run again per sublattice
+    where |M| could have come below 2) and on the per-sublattice kernels, which apply the term
+    phase by phase and are checked against the oracle elsewhere: equal record for record and
+    spin for spin."""
+    from isf_workloads import config_plain_hysteresis_large
+
+    c = config_plain_hysteresis_large()
+    h = c.heights()
+    steps = [(c.T, hn, c.sweeps_per_step, 0, 0, 40) for hn in c.h_nums]
+    w = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    w.attach_aniso_workspace()
+    w.set_tuning(32, 32, 16, True, 3)
+    _say("anisotropic ramp: whole-sweep kernel")
+    rw = w.run_schedule(steps)
+    runs, redone = w.aniso_stats()
+    _say("anisotropic ramp: %d steps on the whole-sweep kernel, %d of them run again" % (runs, redone))
+    p = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+    p.set_tuning(64, 4, 2, True, 0)
+    _say("anisotropic ramp: per-sublattice kernels")
+    rp = p.run_schedule(steps)
+    np.testing.assert_array_equal(rw, rp)
+    np.testing.assert_array_equal(w.spins(), p.spins())
+    M = rp[:, 0]
+    assert M.min() < 0 < M[-1], "the loop must reverse"
+    assert 0 < redone < runs < len(steps) + 1
+
+
 @pytest.mark.timeout(900)
 def test_batched_all_replicas_prefix_and_whole_ramps(isf):
     import torch
