@@ -300,7 +300,7 @@ def bench_batched(args):
     return out
 
 
-def serving_inputs(args):
+def serving_inputs(args, rate=50.0, duration=None):
     """Requests and their height maps (the requests' payload, not server work),
     built in this process with a pool of threads (numpy's FFTs release the GIL)
     only when the serving measurement runs."""
@@ -308,7 +308,7 @@ def serving_inputs(args):
 
     from isf_workloads import height_map, serving_requests
 
-    reqs = serving_requests(duration=args.serve_duration)
+    reqs = serving_requests(rate=rate, duration=duration or args.serve_duration)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
         heights = list(ex.map(lambda q: height_map(q.X, q.Y, q.Z, q.sigma, q.seed), reqs))
@@ -316,9 +316,10 @@ def serving_inputs(args):
     return reqs, {q.rid: hh for q, hh in zip(reqs, heights)}
 
 
-def bench_serving(args, reqs, hmap):
+def bench_serving(args, reqs, hmap, rate=50.0, duration=None):
     """Poisson arrivals (50 req/s for the configured duration) of hysteresis and
     temperature-scan jobs on films of 64^2..2048^2 x 1..10 layers."""
+    duration = duration or args.serve_duration
     from paper_1205_5588_amd.serve import GpuExecutor, Job, Server
 
     jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q), n_sweeps=q.n_sweeps, payload=q)
@@ -331,9 +332,9 @@ def bench_serving(args, reqs, hmap):
     wall = time.perf_counter() - t0
     s = stats.summary()
     s["wall_s"] = round(wall, 2)
-    s["offered_attempts_per_s"] = round(s["attempts"] / args.serve_duration, 1)
+    s["offered_attempts_per_s"] = round(s["attempts"] / duration, 1)
     s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[args.serve_mode]
-    s["arrivals"] = "Poisson 50 req/s for %g s" % args.serve_duration
+    s["arrivals"] = "Poisson %g req/s for %g s" % (rate, duration)
     return s
 
 
@@ -542,6 +543,12 @@ def main():
         if not args.no_serve:
             extra["serving"] = bench_serving(args, *serving_inputs(args))
             log("serving:", extra["serving"])
+            # the same request mix at 15 req/s for 30 s, below the GPU's capacity, where
+            # the latency is service time rather than backlog
+            d = min(30.0, args.serve_duration)
+            extra["serving_below_capacity"] = bench_serving(args, *serving_inputs(args, 15.0, d), rate=15.0,
+                                                            duration=d)
+            log("serving below capacity:", extra["serving_below_capacity"])
 
     cpu_base = None
     if not args.no_cpu:

@@ -101,8 +101,8 @@ typedef struct {
     uint32_t n_discard; /* <= n_sweeps; sweeps not summed into the record */
     int32_t hs_num;     /* switching-field gate, Eq. 9 and steps 4-5 of Section 5: h_s = hs_num / 20,
                            |hs_num| <= 200000; a site may flip only if its gate draw (Philox tag 2) is below
-                           floor(2^32 exp(-|h_s|/T)) and the Metropolis test passes; 0: no gate.  INT8
-                           films only (EINVAL for a bit-packed film) */
+                           floor(2^32 exp(-|h_s|/T)) and the Metropolis test passes; 0: no gate.  Both
+                           formats, every kernel and batch mode */
     int32_t an_num;     /* anisotropy field of Eq. 7 (Section 5): the energy gains -h_an |M| with
                            h_an = an_num / 20, 0 <= an_num <= 200000; 0: no anisotropy.  M couples every
                            site, so it is frozen at its value when each sublattice phase starts: a flip of

@@ -1148,8 +1148,6 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
     uint64_t total = 0;
     for (uint32_t i = 0; i < n; ++i) {
         sd[i] = StepDesc{steps[i].n_sweeps, steps[i].n_discard};
-        if (steps[i].hs_num != 0 && lat->d.format != ISF_FORMAT_INT8)
-            return fail(ISF_EINVAL, "step %u: the switching-field gate needs an INT8 film", i);
         if (steps[i].an_num != 0) {
             if (lat->d.format != ISF_FORMAT_INT8)
                 return fail(ISF_EINVAL, "step %u: the anisotropy term needs an INT8 film", i);

@@ -353,6 +353,7 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
     const uint32_t Y = L.Y, half = Y >> 1;
     uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
     const bool left = ((py ^ pz) == 0);
+    const uint32_t gthr = tab[kGateWord];  // kSentinel: no gate
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const uint32_t yi = (by * RY + r) * TY + ty;
@@ -371,7 +372,7 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
             const uint32_t occ4 = (nb.occ >> (4 * g)) & 0xFu;
             if (!occ4)
                 continue;
-            uint32_t u[4];
+            uint32_t u[4], fg = 0;
             philox(g0 + g, t, L.replica, sigma, L.key0, L.key1, u);
             // the table indices of the group's 4 sites, one byte each: the
             // group's nibble of each bit plane is spread to bit 0 of 4 bytes
@@ -385,8 +386,19 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
             for (int j = 0; j < 4; ++j) {
                 const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
                 const bool ok = ((occ4 >> j) & 1u) && (thr == kSentinel || u[j] < thr);
-                F |= (uint32_t)ok << (4 * g + j);
+                fg |= (uint32_t)ok << j;
             }
+            // the switching-field gate of Eq. (9): the group's own draw (tag 2),
+            // needed only where a Metropolis test passed
+            if (fg && gthr != kSentinel) {
+                philox(g0 + g, t, L.replica, sigma + 8u, L.key0, L.key1, u);
+                uint32_t m = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    m |= (uint32_t)(u[j] < gthr) << j;
+                fg &= m;
+            }
+            F |= fg << (4 * g);
         }
         if (F) {
             const uint32_t fu = F & nb.spin, fd = F & ~nb.spin;

@@ -620,7 +620,7 @@ GATED_STEPS = [(2.5, 30, 7, 0, 40), (0.8, -45, 4, 1, 160), (9.0, 0, 5, 2, -20), 
                                            (2, (16, 16, 4)), (3, (32, 16, 16))])
 @pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1), (352, 46, 6)])
 def test_gated_schedule_matches_oracle(isf, kernel, tiling, X, Y, Z):
-    if kernel == 3 and (X % 32 or X // 8 < tiling[0] + 8 or Y < tiling[1] + 8):
+    if kernel == 3 and (X // 8 < tiling[0] + 8 or Y < tiling[1] + 8):
         pytest.skip("film outside the pipelined kernel's shapes")
     h = _rand_h((Y, X), Z, 11 * X + Y + Z)
     g, o = _pair(isf, h, Z, 97531, replica=8, init=2)
@@ -659,13 +659,38 @@ def test_gated_batch_equals_oracle(isf, mode):
         np.testing.assert_array_equal(lat.spins(), o.spins())
 
 
-def test_gate_rejected_for_bitpacked_films(isf):
-    from paper_1205_5588_amd._lib import IsfError
+@pytest.mark.parametrize("tiling", [(64, 4, 1), (32, 8, 1), (16, 16, 2)])
+@pytest.mark.parametrize("X,Y,Z", [(128, 16, 3), (256, 46, 5), (64, 4, 1)])
+def test_gated_bitpacked_matches_oracle_and_int8(isf, tiling, X, Y, Z):
+    """The gate on the bit-packed kernel: each group of four sites draws its gate numbers
+    where a Metropolis test passed; the same trajectory as the oracle and the INT8 film."""
+    h = _rand_h((Y, X), Z, 5 * X + Y + Z)
+    g, o = _pair(isf, h, Z, 97531, replica=8, init=2, fmt=1)
+    g.set_tuning(tiling[0], tiling[1], tiling[2], True, 0)
+    _say("gated bit-packed", tiling, X, Y, Z)
+    rg = g.run_schedule(GATED_STEPS)
+    np.testing.assert_array_equal(rg, np.array([o.run(*s).as_tuple() for s in GATED_STEPS]))
+    _assert_same(g, o)
+    i8 = isf.Lattice(h, Z, 97531, replica=8, init=2)
+    np.testing.assert_array_equal(i8.run_schedule(GATED_STEPS), rg)
+    np.testing.assert_array_equal(i8.spins(), g.spins())
 
-    g = isf.Lattice(_rand_h((16, 128), 3, 4), 3, 1, fmt=1)
-    with pytest.raises(IsfError):
-        g.run_schedule([(2.0, 0, 3, 0, 40)])
-    g.run_schedule([(2.0, 0, 3, 0, 0)])  # no gate: fine
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gated_bitpacked_batch_equals_oracle(isf, mode):
+    rng = np.random.default_rng(5)
+    films = []
+    for i, (X, Y, Z) in enumerate([(64, 40, 3), (192, 64, 5), (128, 16, 2)]):
+        h = rng.integers(0, Z + 1, size=(Y, X)).astype(np.uint8)
+        sched = [(float(rng.uniform(1.0, 6.0)), int(hv), 3, 0, 40 * (i + 1)) for hv in rng.integers(-60, 61, size=4)]
+        films.append((h, Z, 700 + i, i, sched))
+    lats = [isf.Lattice(h, Z, s, replica=r, init=2, fmt=1) for (h, Z, s, r, sc) in films]
+    _say("gated bit-packed batch", mode)
+    recs = isf.Batch(len(lats)).run(lats, [f[4] for f in films], mode=mode)
+    for (h, Z, s, r, sc), lat, rec in zip(films, lats, recs):
+        o = cpu.Film(h, Z, s, r, init=2)
+        np.testing.assert_array_equal(rec, np.array([o.run(*st).as_tuple() for st in sc]))
+        np.testing.assert_array_equal(lat.spins(), o.spins())
 
 
 # ------------------------------------------------------------------ PMOKE image and film statistics
