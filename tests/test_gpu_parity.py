@@ -864,6 +864,21 @@ def test_aniso_rejected_where_unsupported(isf):
     g.set_tuning(32, 16, 16, True, 3)
     assert g.advance(2) == 2
     o.run(2.0, 10, 2)
+    # the workspace: refused for a bit-packed film, short or misaligned buffers
+    import ctypes
+
+    import torch
+
+    from paper_1205_5588_amd import _lib
+
+    nb = ctypes.c_uint64()
+    assert _lib.load().isf_aniso_workspace_bytes(bp.handle, ctypes.byref(nb)) == _lib.ISF_EINVAL
+    assert _lib.load().isf_aniso_workspace_bytes(g.handle, ctypes.byref(nb)) == 0
+    buf = torch.empty(int(nb.value) + 512, dtype=torch.uint8, device="cuda")
+    lib = _lib.load()
+    assert lib.isf_attach_aniso_workspace(g.handle, buf.data_ptr(), int(nb.value) - 1) == _lib.ISF_ENOSPC
+    assert lib.isf_attach_aniso_workspace(g.handle, buf.data_ptr() + 16, int(nb.value)) == _lib.ISF_EINVAL
+    assert lib.isf_attach_aniso_workspace(g.handle, None, int(nb.value)) == _lib.ISF_EINVAL
     # with a workspace the whole-sweep kernels take the term too
     g.attach_aniso_workspace()
     g.schedule_load([(2.0, 0, 3, 0, 0, 40)])
