@@ -148,9 +148,13 @@ struct AnisoLoads {
     uint32_t plus, minus;  // word `lane` (< 50) of the tables of q + an and q - an
 };
 
-__device__ __forceinline__ AnisoLoads aniso_issue(const LatDev &L, uint32_t lane) {
+__device__ __forceinline__ AnisoLoads aniso_issue(const LatDev &L, uint32_t sigma, uint32_t lane) {
     AnisoLoads a;
-    a.dM = L.slots[lane].dM;
+    // the changes of M in this sweep's earlier phases (all of their blocks have
+    // added them: earlier launches); this phase's blocks add to dM_phase[sigma]
+    a.dM = 0;
+    for (uint32_t j = 0; j < sigma; ++j)
+        a.dM += L.slots[lane].dM_phase[j];
     a.M = L.st->M;
     a.plus = lane < 50 ? L.st->cur_atable[lane] : 0u;
     a.minus = lane < 50 ? L.st->cur_atable[50 + lane] : 0u;
@@ -236,6 +240,11 @@ __device__ inline void sweep_end(const LatDev &L) {
         sst<kAtomic>(&L.slots[s].dM, (int64_t)0);
         sst<kAtomic>(&L.slots[s].dE, (int64_t)0);
         sst<kAtomic>(&L.slots[s].acc, (int64_t)0);
+        if (L.aniso) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                sst<kAtomic>(&L.slots[s].dM_phase[j], (int64_t)0);
+        }
     }
     dM = wave_sum(dM);
     dE = wave_sum(dE);
@@ -300,8 +309,11 @@ __device__ inline void sweep_end(const LatDev &L) {
 // last block is found behind a device-scope fence per block (an L2 write-back
 // each) or through returning atomics (a memory round trip before every block
 // can retire).
+// phase >= 0: an anisotropic sublattice phase, whose change of M also goes to
+// the slot's dM_phase[phase] (read by the sweep's later phases).
 template <int NT>
-__device__ __forceinline__ void finish_block_to(Slot *slots, int dM, int dE, int acc, uint32_t block_in_lat) {
+__device__ __forceinline__ void finish_block_to(Slot *slots, int dM, int dE, int acc, uint32_t block_in_lat,
+                                                int phase = -1) {
     __shared__ int red[3][NT / 64];
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     dM = wave_sum(dM);
@@ -326,14 +338,17 @@ __device__ __forceinline__ void finish_block_to(Slot *slots, int dM, int dE, int
             aadd(&slot->dM, sM);
             aadd(&slot->dE, sE);
             aadd(&slot->acc, sA);
+            if (phase >= 0)
+                aadd(&slot->dM_phase[phase], sM);
         }
     }
     __syncthreads();
 }
 
 template <int NT>
-__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat) {
-    finish_block_to<NT>(L.slots, dM, dE, acc, block_in_lat);
+__device__ __forceinline__ void finish_block(const LatDev &L, int dM, int dE, int acc, uint32_t block_in_lat,
+                                             int phase = -1) {
+    finish_block_to<NT>(L.slots, dM, dE, acc, block_in_lat, phase);
 }
 
 // Block-wide sum of four 64-bit values into out[0..3] (256-thread blocks).

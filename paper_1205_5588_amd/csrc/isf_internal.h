@@ -63,7 +63,10 @@ struct alignas(128) Slot {
     int64_t dM;
     int64_t dE;
     int64_t acc;
-    int64_t pad[13];
+    // anisotropic sweeps: the change of M in each sublattice phase, kept apart
+    // so that a phase reads the earlier phases' changes and never its own
+    int64_t dM_phase[4];
+    int64_t pad[9];
 };
 
 struct StepDesc {

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(TX *TY) void k_phase_i8(LatDev L, uint32_t sigma) {
     int dM = 0, dE = 0, acc = 0;
     phase_block_i8<TX, TY, RY, false>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, dM, dE, acc);
     const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    finish_block<TX * TY>(L, dM, dE, acc, blin);
+    finish_block<TX * TY>(L, dM, dE, acc, blin, L.aniso ? (int)sigma : -1);
 }
 
 // Batched: one launch covers the same sublattice of many films.  Block b
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
     const bool aniso = L.aniso && tid < 64;  // uniform over each wave
     AnisoLoads an{};
     if (aniso)
-        an = aniso_issue(L, tid);
+        an = aniso_issue(L, sigma, tid);
     const uint32_t n = L.n_items[sigma];
     const uint32_t *items = L.items + L.items_off[sigma];
     const uint32_t Y = L.Y, nd = L.nd, rowb = nd * 4u;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
             *reinterpret_cast<uint32_t *>(base + self_off[k]) = a ^ F;
         }
     }
-    finish_block<256>(L, dM, dE, acc, blockIdx.x);
+    finish_block<256>(L, dM, dE, acc, blockIdx.x, L.aniso ? (int)sigma : -1);
 }
 
 // --------------------------------------------------------------------------

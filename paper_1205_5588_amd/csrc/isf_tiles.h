@@ -115,7 +115,7 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
     const bool aniso = !kAtomic && L.aniso && wid == 0;  // uniform over each wave
     AnisoLoads an{};
     if (aniso)
-        an = aniso_issue(L, lane);
+        an = aniso_issue(L, sigma, lane);
 
     const uint32_t py = sigma & 1u, pz = sigma >> 1;
     const uint32_t z = 2 * bz + pz;
@@ -340,9 +340,12 @@ __device__ __forceinline__ Idx6 table_index(const Cnt4 &U, const Cnt4 &D, uint32
     return r;
 }
 
-template <int TX, int TY, int RY>
-__device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
-                                              const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
+// kGate: the step has the switching-field gate (its code is compiled out of
+// the ungated path, where it cost 3 % of a sweep).
+template <int TX, int TY, int RY, bool kGate>
+__device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by,
+                                                uint32_t bz, const uint32_t *tab, uint32_t t, int &dM, int &dE,
+                                                int &acc) {
     const uint32_t py = sigma & 1u, pz = sigma >> 1;
     const uint32_t z = 2 * bz + pz;
     const uint32_t tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -353,7 +356,7 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
     const uint32_t Y = L.Y, half = Y >> 1;
     uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
     const bool left = ((py ^ pz) == 0);
-    const uint32_t gthr = tab[kGateWord];  // kSentinel: no gate
+    const uint32_t gthr = kGate ? tab[kGateWord] : kSentinel;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const uint32_t yi = (by * RY + r) * TY + ty;
@@ -390,7 +393,7 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
             }
             // the switching-field gate of Eq. (9): the group's own draw (tag 2),
             // needed only where a Metropolis test passed
-            if (fg && gthr != kSentinel) {
+            if (kGate && fg) {
                 philox(g0 + g, t, L.replica, sigma + 8u, L.key0, L.key1, u);
                 uint32_t m = 0;
 #pragma unroll
@@ -416,6 +419,15 @@ __device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, u
             P[((size_t)(z + 1) * Y + y) * 2 * nw + w] = nb.spin ^ F;
         }
     }
+}
+
+template <int TX, int TY, int RY>
+__device__ __forceinline__ void phase_tile_bp(const LatDev &L, uint32_t sigma, uint32_t bx, uint32_t by, uint32_t bz,
+                                              const uint32_t *tab, uint32_t t, int &dM, int &dE, int &acc) {
+    if (tab[kGateWord] == kSentinel)  // uniform: the step has no gate
+        phase_tile_bp_g<TX, TY, RY, false>(L, sigma, bx, by, bz, tab, t, dM, dE, acc);
+    else
+        phase_tile_bp_g<TX, TY, RY, true>(L, sigma, bx, by, bz, tab, t, dM, dE, acc);
 }
 
 }  // namespace isf

@@ -207,6 +207,24 @@ def test_large_ramp_anisotropy_whole_kernel_equals_phase_kernels(isf):
     M = rp[:, 0]
     assert M.min() < 0 < M[-1], "the loop must reverse"
     assert 0 < redone < runs < len(steps) + 1
+    # the oracle on the two steps where M changes sign (the per-sublattice kernels'
+    # phases read M from many blocks there), each from the GPU's spins at its start
+    n = len(steps)
+    down = int(np.argmax(M < 0))
+    up = n // 2 + int(np.argmax(M[n // 2:] > 0))
+    cpu.set_threads(_workers())
+    for s in (down, up):
+        q = isf.Lattice(h, c.Z, c.mc_seed, init=c.init)
+        q.set_tuning(64, 4, 2, True, 0)
+        q.run_schedule(steps[:s])
+        start = q.spins()
+        np.testing.assert_array_equal(q.run_schedule(steps[s:s + 1])[0], rp[s])
+        _say("anisotropic ramp: oracle on step %d (M %d -> %d)" % (s, M[s - 1], M[s]))
+        f = cpu.Film(h, c.Z, c.mc_seed, init=c.init)
+        f.set_spins(start, s * c.sweeps_per_step)
+        assert f.run(*steps[s]).as_tuple() == tuple(rp[s]), s
+        np.testing.assert_array_equal(f.spins(), q.spins())
+        del q
 
 
 @pytest.mark.timeout(900)
