@@ -93,6 +93,9 @@ class ServerStats:
         t_first = min(r.arrival for r in self.results)
         t_last = max(r.finished for r in self.results)
         att = sum(r.attempts for r in self.results)
+        # accepted flips in the records' kept sweeps (a T-scan step's discarded
+        # sweeps are not counted)
+        acc = sum(int(np.asarray(r.records)[:, 5].sum()) for r in self.results if len(r.records))
         return {
             "requests": len(self.results),
             "p50_s": float(np.percentile(lat, 50)),
@@ -102,6 +105,8 @@ class ServerStats:
             "attempts": int(att),
             "span_s": float(t_last - t_first),
             "attempts_per_s": float(att / max(t_last - t_first, 1e-9)),
+            "accepted_kept": int(acc),
+            "accepted_kept_per_s": float(acc / max(t_last - t_first, 1e-9)),
             "max_active": self.max_active,
             "max_bytes": self.max_bytes,
             "chunks": self.chunks,
