@@ -336,7 +336,14 @@ def bench_serving(args, reqs, hmap, rate=50.0, duration=None):
     srv = Server(ex, budget_bytes=int(args.serve_budget_gib * 2**30), max_slots=args.serve_slots,
                  target_chunk_s=0.02, rate_estimate=2e11, max_chunk=64)
     t0 = time.perf_counter()
-    stats = srv.run(jobs)
+    done = [0]
+
+    def retired(_res):
+        done[0] += 1
+        if done[0] % 500 == 0:
+            log("serving: %d of %d requests done after %.0f s" % (done[0], len(jobs), time.perf_counter() - t0))
+
+    stats = srv.run(jobs, on_retire=retired)
     wall = time.perf_counter() - t0
     s = stats.summary()
     s["wall_s"] = round(wall, 2)
