@@ -353,6 +353,57 @@ def bench_serving(args, reqs, hmap, rate=50.0, duration=None):
     return s
 
 
+def bench_small_configs(tune=True):
+    """The two other plain workloads, whole, with HIP events around each: the small
+    ramp (64x64x3, 161 field steps x 100 sweeps, launch- and latency-bound: a
+    6 KiB film, so no roofline) and the temperature scan (512x512x5, 45
+    temperatures x 1000 sweeps, the first 200 of each discarded), each in the
+    launch shape the tuner picks for it."""
+    import torch
+
+    from isf_workloads import config_plain_hysteresis_small, config_plain_tscan
+    from paper_1205_5588_amd.autotune import lookup, tune_lattice
+    from paper_1205_5588_amd.lattice import Lattice
+
+    out = {}
+    for name, cfg in (("small_ramp", config_plain_hysteresis_small()), ("temperature_scan", config_plain_tscan())):
+        h = cfg.heights()
+        T0, h0 = (cfg.T, cfg.h_nums[0]) if cfg.h_nums is not None else (cfg.temps[-1], 0)
+        if tune:
+            tb = tune_lattice(lambda: Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init), 0, T0, h0, sweeps=64,
+                              warmup=4)
+            tl = tuple(tb["tiling"]) + (tb["use_graph"], tb["kernel"])
+        else:
+            tl = lookup(cfg.X, cfg.Y, cfg.Z, 0)
+        lat = Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init)
+        lat.set_tuning(*tl)
+        if cfg.h_nums is not None:
+            sched = [(cfg.T, hv, cfg.sweeps_per_step, 0) for hv in cfg.h_nums]
+        else:
+            sched = [(T, 0, cfg.sweeps_per_T, cfg.discard_per_T) for T in cfg.temps]
+        sweeps = sum(s[2] for s in sched)
+        lat.run_schedule(sched[:1])  # warm-up: graphs and lists built
+        lat.schedule_load(sched)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        while lat.advance(1 << 20):
+            pass
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        n_occ = lat.observables()["n_occ"]
+        out[name] = {"film": "%dx%dx%d" % (cfg.X, cfg.Y, cfg.Z), "sweeps": sweeps,
+                     "attempts_per_s": round(n_occ * sweeps / (ms * 1e-3), 1),
+                     "us_per_sweep": round(ms * 1e3 / sweeps, 3), "tuning": list(tl),
+                     "hbm_frac_5Nc": None if name == "small_ramp" else
+                     round(5 * (cfg.X * cfg.Y * cfg.Z // 2) / (ms * 1e-3 / sweeps) / 1e9 / HBM_PEAK_GBS, 4)}
+        if name == "small_ramp":
+            out[name]["roofline"] = "n/a: launch- and latency-bound"
+        del lat
+    return out
+
+
 def cpu_baseline(cfg, h, budget_s=15.0):
     from oracle import cpu
 
@@ -534,7 +585,10 @@ def main():
     log("pmoke image:", pmoke)
     del lat
 
+    small = bench_small_configs(tune=not args.no_tune)
+    log("small configs:", small)
     extra = {"whole_ramp": ramp_summary(r, cfg)["whole_ramp"], "alu_ceiling": ceiling, "pmoke_image": pmoke,
+             "other_plain_workloads": small,
              "film": lat_stats,
              "tuning": {"tiling": list(tuning[:3]), "use_graph": bool(tuning[3]), "kernel": int(tuning[4]),
                         "tuned": tune_info is not None,
