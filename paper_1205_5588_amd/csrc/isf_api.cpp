@@ -599,7 +599,8 @@ void spec_advance_pos(isf_lattice *lat, uint64_t n) {
     }
 }
 
-// M and the current step's accepted count, read from the device state.
+// The device state (into head, synchronously) and its M, the magnetisation at
+// the host's copy of the schedule position.
 int32_t spec_read(isf_lattice *lat, DevState *head) {
     int32_t rc = flush_whole(lat);
     if (rc)
