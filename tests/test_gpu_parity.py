@@ -396,6 +396,30 @@ def test_sweep_kernel_rejects_unsupported(isf):
     assert g.get_tuning()[4] == 0  # rejected shapes leave the previous tuning
 
 
+@pytest.mark.parametrize("fmt,kernel,tiling", [(0, 0, (64, 4, 2)), (0, 0, (16, 16, 1)),
+                                               (1, 0, (64, 4, 1)), (1, 0, (16, 16, 2))])
+def test_max_depth_film_matches_oracle(isf, fmt, kernel, tiling):
+    """Films of the deepest allowed stack, Z = 64 layers (and a column height of 64 in
+    places), on the kernels that take them, against the oracle.  The whole-sweep
+    kernels hold the tile's whole column in LDS and refuse such films (even the
+    16 x 16 tile needs about 178 KiB at Z = 64)."""
+    from paper_1205_5588_amd._lib import IsfError
+
+    X, Y, Z = 64, 16, 64
+    h = _rand_h((Y, X), Z, 64)
+    h[0, :] = Z
+    g, o = _pair(isf, h, Z, 6464, replica=3, init=2, fmt=fmt)
+    if fmt == 0:
+        for shape in ((16, 16, 4, 2), (32, 8, 4, 2), (32, 16, 8, 3)):
+            with pytest.raises(IsfError):
+                g.set_tuning(shape[0], shape[1], shape[2], True, shape[3])
+    g.set_tuning(tiling[0], tiling[1], tiling[2], True, kernel)
+    _say("max depth film", fmt, kernel, tiling)
+    steps = [(3.0, 20, 6, 1), (8.0, -30, 5, 0, 40), (1e-3, 0, 2, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*st).as_tuple() for st in steps]))
+    _assert_same(g, o)
+
+
 def test_sweep_kernel_large_prefix(isf):
     from isf_workloads import config_plain_hysteresis_large
 
