@@ -483,10 +483,13 @@ def test_sweep_kernel_switches_and_reads_midway(isf):
 
 # ------------------------------------------------------------------ pipelined whole-sweep kernel
 # (film, shape): rows of whole 16-byte pieces (X a multiple of 32), at least one
-# region (tile + 4 dwords / 4 rows a side) wide and high; ragged tiles in x and y
+# region (tile + 4 dwords / 4 rows a side) wide and high; ragged tiles in x and y;
+# each shape at the deepest film its two LDS buffers hold (32 x 16: Z = 14,
+# 32 x 32: Z = 8, 64 x 16: Z = 7), one of them on rows that are not whole pieces
 PIPE_CASES = [((320, 24, 5), (32, 16, 16)), ((352, 42, 6), (32, 16, 8)), ((576, 40, 9), (32, 16, 16)),
               ((384, 64, 1), (32, 32, 16)), ((352, 72, 8), (32, 32, 8)), ((640, 50, 3), (64, 16, 16)),
-              ((1280, 960, 3), (32, 16, 16))]
+              ((1280, 960, 3), (32, 16, 16)), ((320, 32, 14), (32, 16, 16)), ((328, 30, 14), (32, 16, 8)),
+              ((576, 24, 7), (64, 16, 16))]
 
 
 @pytest.mark.parametrize("film,tiling", PIPE_CASES)
@@ -540,6 +543,10 @@ def test_pipe_kernel_rejects_unsupported(isf):
             isf.Lattice(hh, Z, 1).set_tuning(32, 16, 16, False, 3)
     with pytest.raises(IsfError):
         isf.Lattice(_rand_h((64, 512), 9, 5), 9, 1).set_tuning(32, 32, 16, False, 3)  # 32 x 32 at Z = 9
+    with pytest.raises(IsfError):
+        isf.Lattice(_rand_h((32, 320), 15, 6), 15, 1).set_tuning(32, 16, 16, False, 3)  # 32 x 16 at Z = 15
+    with pytest.raises(IsfError):
+        isf.Lattice(_rand_h((24, 576), 8, 7), 8, 1).set_tuning(64, 16, 16, False, 3)  # 64 x 16 at Z = 8
     assert g.get_tuning()[4] == 0  # rejected shapes leave the previous tuning
 
 
