@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
         t_sh = tv;
     __syncthreads();
     const uint32_t t = t_sh;
+    const PhiloxShared psh = philox_shared(t, L.replica, L.key0);  // the parts of the counter every item shares
     int dM = 0, dE = 0, acc = 0;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
@@ -143,13 +144,17 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
         if (!ok[k] || !occ)
             continue;
         uint32_t u[4];
-        philox(pos[k], t, L.replica, sigma, L.key0, L.key1, u);
-        const uint32_t key = sum + ((a >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1]
+        philox_first_two(u, pos[k], sigma, psh, L.key0, L.key1);
+        philox_rounds<2, 10>(u, L.key0, L.key1);
+        const uint32_t up = (a >> 1) & 0x01010101u;
+        const uint32_t key = sum + up + (up << 3) + (up << 4);  // n + 12 + 25 [s = +1]
         uint32_t F = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            // downhill thresholds are kSentinel and every other one is below it,
+            // so with u clamped to kSentinel - 1 one test is exact
             const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
-            F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
+            F |= (min(u[j], kSentinel - 1u) < thr) ? (2u << (8 * j)) : 0u;
         }
         F &= occ << 1;
         if (F)
@@ -157,8 +162,8 @@ __global__ __launch_bounds__(256) void k_phase_i8_list(LatDev L, uint32_t sigma)
         if (F) {
             const uint32_t fu = F & a, fd = F ^ fu;
             const int cu = __popc(fu), cd = __popc(fd);
-            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
-            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t su = __builtin_amdgcn_udot4(sum, fu >> 1, 0u, false);  // neighbour sums of the up flips
+            const uint32_t sd = __builtin_amdgcn_udot4(sum, fd >> 1, 0u, false);  // and of the down flips
             dM += 2 * (cd - cu);
             dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
             acc += cu + cd;

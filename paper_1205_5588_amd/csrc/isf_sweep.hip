@@ -538,6 +538,7 @@ __device__ __forceinline__ void sweep_tile(const LatDev &L, const uint8_t *__res
 
     int dM = 0, dE = 0, acc = 0;
     const uint32_t t = t_sh;
+    const PhiloxShared psh = philox_shared(t, L.replica, L.key0);  // the sweep's common draw parts
     const uint32_t c4[4] = {cnt.x, cnt.y, cnt.z, cnt.w};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -580,8 +581,10 @@ __device__ __forceinline__ void sweep_tile(const LatDev &L, const uint8_t *__res
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 uint32_t u[4];
-                philox(kb[k] + (dm[k] & 0x7FFFFFFFu), t, L.replica, (uint32_t)s, L.key0, L.key1, u);
-                const uint32_t key = sum[k] + ((a[k] >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1], <= 49
+                philox_first_two(u, kb[k] + (dm[k] & 0x7FFFFFFFu), (uint32_t)s, psh, L.key0, L.key1);
+                philox_rounds<2, 10>(u, L.key0, L.key1);
+                const uint32_t up = (a[k] >> 1) & 0x01010101u;
+                const uint32_t key = sum[k] + up + (up << 3) + (up << 4);  // n + 12 + 25 [s = +1], <= 49
                 uint32_t f = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -605,8 +608,8 @@ __device__ __forceinline__ void sweep_tile(const LatDev &L, const uint8_t *__res
                     if ((ym[k] & dm[k]) >> 31) {  // a dword of this block's tile
                         const uint32_t fu = F[k] & a[k], fd = F[k] ^ fu;
                         const int cu = __popc(fu), cd = __popc(fd);
-                        const uint32_t su = __builtin_amdgcn_sad_u8(sum[k] & ((fu >> 1) * 0xFFu), 0u, 0u);
-                        const uint32_t sd = __builtin_amdgcn_sad_u8(sum[k] & ((fd >> 1) * 0xFFu), 0u, 0u);
+                        const uint32_t su = __builtin_amdgcn_udot4(sum[k], fu >> 1, 0u, false);
+                        const uint32_t sd = __builtin_amdgcn_udot4(sum[k], fd >> 1, 0u, false);
                         dM += 2 * (cd - cu);
                         dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
                         acc += cu + cd;
@@ -993,8 +996,8 @@ __device__ __forceinline__ void pipe_attempt(uint32_t qi, uint32_t *Rb, const ui
         if ((rk & dm) >> 31) {  // a dword of this block's tile
             const uint32_t fu = f & a, fd = f ^ fu;
             const int cu = __popc(fu), cd = __popc(fd);
-            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
-            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t su = __builtin_amdgcn_udot4(sum, fu >> 1, 0u, false);  // neighbour sums of the up flips
+            const uint32_t sd = __builtin_amdgcn_udot4(sum, fd >> 1, 0u, false);  // and of the down flips
             dM += 2 * (cd - cu);
             dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
             acc += cu + cd;

@@ -210,6 +210,7 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
     // extra pass is spread over the SIMDs of a CU instead of piling onto one.
     const uint32_t rot = (bx + by + bz) % (NT / 64);
     const uint32_t i0 = ((wid + rot) % (NT / 64)) * 64u + lane;
+    const PhiloxShared psh = philox_shared(t, L.replica, L.key0);  // the parts of the counter every item shares
     for (uint32_t i = i0; i < n_items; i += NT) {
         const uint32_t slot = lslot[i];
         const uint32_t a = lA[i], sum = lS[i];
@@ -218,14 +219,18 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
         const uint32_t dd = bx * TX + st % TX;
         const uint32_t k4 = cz + y * nd + dd;
         uint32_t u[4];
-        philox(k4, t, L.replica, sigma, L.key0, L.key1, u);
+        philox_first_two(u, k4, sigma, psh, L.key0, L.key1);
+        philox_rounds<2, 10>(u, L.key0, L.key1);
         const uint32_t occ = ~a & 0x01010101u;
-        const uint32_t key = sum + ((a >> 1) & 0x01010101u) * 25u;  // n + 12 + 25 [s = +1], <= 49
+        const uint32_t up = (a >> 1) & 0x01010101u;
+        const uint32_t key = sum + up + (up << 3) + (up << 4);  // n + 12 + 25 [s = +1], <= 49
         uint32_t F = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            // thresholds of downhill moves are kSentinel and every other one is
+            // below it, so with u clamped to kSentinel - 1 one test is exact
             const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
-            F |= ((u[j] < thr) | (thr == kSentinel)) ? (2u << (8 * j)) : 0u;
+            F |= (min(u[j], kSentinel - 1u) < thr) ? (2u << (8 * j)) : 0u;
         }
         F &= occ << 1;  // vacancies never flip
         if (F)
@@ -234,8 +239,8 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
             // up spins flipped: byte 2 in a & F; down spins flipped: the rest of F
             const uint32_t fu = F & a, fd = F ^ fu;
             const int cu = __popc(fu), cd = __popc(fd);
-            const uint32_t su = __builtin_amdgcn_sad_u8(sum & ((fu >> 1) * 0xFFu), 0u, 0u);
-            const uint32_t sd = __builtin_amdgcn_sad_u8(sum & ((fd >> 1) * 0xFFu), 0u, 0u);
+            const uint32_t su = __builtin_amdgcn_udot4(sum, fu >> 1, 0u, false);
+            const uint32_t sd = __builtin_amdgcn_udot4(sum, fd >> 1, 0u, false);
             dM += 2 * (cd - cu);
             dE += 2 * ((int)su - (int)sd) - 24 * (cu - cd);
             acc += cu + cd;
@@ -357,6 +362,7 @@ __device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma,
     uint32_t *P = reinterpret_cast<uint32_t *>(L.spins);
     const bool left = ((py ^ pz) == 0);
     const uint32_t gthr = kGate ? tab[kGateWord] : kSentinel;
+    const PhiloxShared psh = philox_shared(t, L.replica, L.key0);  // the parts of the counter every group shares
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const uint32_t yi = (by * RY + r) * TY + ty;
@@ -376,7 +382,8 @@ __device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma,
             if (!occ4)
                 continue;
             uint32_t u[4], fg = 0;
-            philox(g0 + g, t, L.replica, sigma, L.key0, L.key1, u);
+            philox_first_two(u, g0 + g, sigma, psh, L.key0, L.key1);
+            philox_rounds<2, 10>(u, L.key0, L.key1);
             // the table indices of the group's 4 sites, one byte each: the
             // group's nibble of each bit plane is spread to bit 0 of 4 bytes
             // (bit j of a nibble n lands on bit 8j of n * 0x204081; the four
@@ -388,7 +395,7 @@ __device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma,
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
-                const bool ok = ((occ4 >> j) & 1u) && (thr == kSentinel || u[j] < thr);
+                const bool ok = ((occ4 >> j) & 1u) && min(u[j], kSentinel - 1u) < thr;  // exact: see phase_block_i8
                 fg |= (uint32_t)ok << j;
             }
             // the switching-field gate of Eq. (9): the group's own draw (tag 2),
