@@ -69,8 +69,8 @@ enum { ISF_INIT_UP = 0, ISF_INIT_DOWN = 1, ISF_INIT_RANDOM = 2 };
 
 /* Film description.  X: image width (columns), Y: image height (rows),
  * Z: number of atomic layers (Section 3).
- *   INT8:    X a multiple of 8, X >= 8; Y even, Y >= 4; 1 <= Z <= 64.
- *   BITPACK: X a multiple of 64; same Y and Z limits.
+ *   Both formats: X a multiple of 8, X >= 8; Y even, Y >= 4; 1 <= Z <= 64
+ *   (a BITPACK row of W = X/2 sites takes ceil(W/32) words per bit plane).
  *   Y <= 65536, X * Y / 2 < 2^31 (bytes of one layer), X * Y * Z / 2 < 2^34
  *   (stored sites). */
 typedef struct {

@@ -41,7 +41,7 @@ def shape_key(X: int, Y: int, Z: int, fmt: int) -> str:
 
 def default_tiling(X: int, fmt: int) -> Tuple[int, int, int]:
     """Heuristic sublattice-kernel shape for films not in the cache: widest tile that the row fills."""
-    per_row = X // 8 if fmt == FORMAT_INT8 else X // 64
+    per_row = X // 8 if fmt == FORMAT_INT8 else (X // 2 + 31) // 32
     if per_row >= 64:
         return (64, 4, 2) if fmt == FORMAT_INT8 else (64, 4, 1)
     if per_row >= 32:
@@ -162,8 +162,8 @@ def tune_batch(make_lats: Callable[..., list], schedule_of: Callable[[int], list
     """Time (tile_x, tile_y, rows_or_waves, batch mode) candidates on a batch of films
     (fresh copies per candidate, built by make_lats(fmt)), for each spin format in
     `formats` (default: fmt alone).  Whole-sweep and pipelined modes apply to INT8
-    films only; a format the films cannot take (bit-packed rows need X % 64 == 0)
-    and a candidate the library refuses or that reports a failed run are skipped.
+    films only; a format the films cannot take and a candidate the library
+    refuses or that reports a failed run are skipped.
     Every candidate must give every film the same records and spins."""
     import torch
 

@@ -104,9 +104,8 @@ int32_t validate_desc(const isf_desc *d) {
         return fail(ISF_EINVAL, "isf_desc.reserved must be 0");
     if (d->format != ISF_FORMAT_INT8 && d->format != ISF_FORMAT_BITPACK)
         return fail(ISF_EINVAL, "unknown format %u", d->format);
-    const uint32_t xmul = d->format == ISF_FORMAT_INT8 ? 8 : 64;
-    if (d->X < xmul || d->X % xmul)
-        return fail(ISF_EINVAL, "X=%u must be a positive multiple of %u for this format", d->X, xmul);
+    if (d->X < 8 || d->X % 8)
+        return fail(ISF_EINVAL, "X=%u must be a positive multiple of 8", d->X);
     if (d->Y < 4 || (d->Y & 1))
         return fail(ISF_EINVAL, "Y=%u must be even and >= 4", d->Y);
     if (d->Z < 1 || d->Z > 64)
@@ -135,7 +134,7 @@ uint64_t spin_bytes_of(const isf_desc *d) {
     const uint64_t W = d->X / 2;
     if (d->format == ISF_FORMAT_INT8)
         return (uint64_t)(d->Z + 2) * d->Y * W;
-    return (uint64_t)(d->Z + 2) * d->Y * 2 * (W / 32) * 4;
+    return (uint64_t)(d->Z + 2) * d->Y * 2 * ((W + 31) / 32) * 4;
 }
 
 // The aux buffer: device state, slots, schedule, tables and records, then (INT8)
@@ -729,7 +728,7 @@ void build_layout(const isf_desc &d, const uint8_t *h, std::vector<uint8_t> &buf
                         row[j] = 0;
             }
     } else {
-        const uint32_t nw = W / 32;
+        const uint32_t nw = (W + 31) / 32;
         uint32_t *w = reinterpret_cast<uint32_t *>(buf.data());
         for (uint32_t z = 0; z < Z; ++z)
             for (uint32_t y = 0; y < Y; ++y) {
@@ -895,7 +894,7 @@ int32_t isf_lattice_create(const isf_desc *d, const uint8_t *h_host, int32_t ini
     L.Y = d->Y;
     L.Z = d->Z;
     L.W = d->X / 2;
-    L.nd = d->format == ISF_FORMAT_INT8 ? L.W / 4 : L.W / 32;
+    L.nd = d->format == ISF_FORMAT_INT8 ? L.W / 4 : (L.W + 31) / 32;
     L.key0 = (uint32_t)d->seed;
     L.key1 = (uint32_t)(d->seed >> 32);
     L.replica = d->replica;
@@ -1381,7 +1380,7 @@ int32_t isf_read_spins(isf_lattice *lat, int8_t *cube) {
                 for (uint32_t j = 0; j < W; ++j)
                     out[2 * j + p] = row[j] == 1 ? 0 : (int8_t)((int)row[j] - 1);
             } else {
-                const uint32_t nw = W / 32;
+                const uint32_t nw = (W + 31) / 32;
                 const uint32_t *w = reinterpret_cast<const uint32_t *>(buf.data()) + ((size_t)(z + 1) * Y + y) * 2 * nw;
                 for (uint32_t j = 0; j < W; ++j) {
                     const uint32_t up = (w[j >> 5] >> (j & 31)) & 1u, oc = (w[nw + (j >> 5)] >> (j & 31)) & 1u;
@@ -1422,7 +1421,7 @@ int32_t isf_write_spins(isf_lattice *lat, const int8_t *cube, uint64_t sweeps) {
                     row[j] = (uint8_t)(s + 1);
                 }
             } else {
-                const uint32_t nw = W / 32;
+                const uint32_t nw = (W + 31) / 32;
                 uint32_t *w = reinterpret_cast<uint32_t *>(buf.data()) + ((size_t)(z + 1) * Y + y) * 2 * nw;
                 for (uint32_t j = 0; j < W; ++j) {
                     if (!((w[nw + (j >> 5)] >> (j & 31)) & 1u))
@@ -1662,7 +1661,7 @@ int32_t isf_recount_films(const isf_desc *descs, const void *const *spins_dev, u
         L.Y = d.Y;
         L.Z = d.Z;
         L.W = d.X / 2;
-        L.nd = d.format == ISF_FORMAT_INT8 ? L.W / 4 : L.W / 32;
+        L.nd = d.format == ISF_FORMAT_INT8 ? L.W / 4 : (L.W + 31) / 32;
         L.format = d.format;
         const hipError_t e = d.format == ISF_FORMAT_INT8 ? launch_recount_i8(L, cnt + 4 * i, s)
                                                          : launch_recount_bp(L, cnt + 4 * i, s);

@@ -1,7 +1,8 @@
 // HIP kernels for gfx950: the BITPACK storage format (one spin bit and one
-// occupancy bit per site, 32 compact sites per word; layout in
-// isf_internal.h).  Same draws, same thresholds, same visiting rule as the
-// INT8 kernels, so the trajectory is identical.
+// occupancy bit per site, 32 compact sites per word, the last word of a row
+// partly filled where W is not a multiple of 32; layout in isf_internal.h).
+// Same draws, same thresholds, same visiting rule as the INT8 kernels, so the
+// trajectory is identical.
 //
 // A thread owns one word (32 consecutive compact sites of one row = 8 Philox
 // calls).  For the 12 neighbour rows it forms, bit-sliced over the 32 sites,
@@ -62,7 +63,7 @@ __global__ void k_init_bp(LatDev L, int32_t mode) {
         v = occ;
     } else if (mode == ISF_INIT_RANDOM && occ) {
         const uint32_t sigma = (y & 1u) + 2u * (z & 1u);
-        const uint32_t g0 = ((z * L.Y + y) * nw + w) * 8u;
+        const uint32_t g0 = (z * L.Y + y) * (L.W / 4u) + 8u * w;  // as in the phase kernel
         for (int g = 0; g < 8; ++g) {
             if (!((occ >> (4 * g)) & 0xFu))
                 continue;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_recount_bp(LatDev L, int64_t *out) {
         const uint32_t w = (uint32_t)(g % L.nd), row = (uint32_t)(g / L.nd);
         const uint32_t y = row % L.Y, z = row / L.Y;
         const bool left = (((y ^ z) & 1u) == 0);
-        const NbBits r = gather_bp(reinterpret_cast<const uint32_t *>(L.spins), L.Y, L.nd, y, z, w, left);
+        const NbBits r = gather_bp(reinterpret_cast<const uint32_t *>(L.spins), L.Y, L.nd, L.W, y, z, w, left);
         for (int i = 0; i < 32; ++i) {
             if (!((r.occ >> i) & 1u))
                 continue;

@@ -10,9 +10,10 @@
 //   [0, 24] (a vacancy adds 1 = 0 + 1).  Four sites share one dword and
 //   twelve dwords add without carries between bytes.
 //
-// BITPACK format: per row two bit planes of W bits (W/32 words each): spin
-//   bit (1 = up) and occupancy bit; planes z = -1 and z = Z are zero words.
-//   Layout [Z+2][Y][2][W/32] uint32 (spin words then occupancy words).
+// BITPACK format: per row two bit planes of W bits (nw = ceil(W/32) words
+//   each): spin bit (1 = up) and occupancy bit; the bits of the last word past
+//   column W - 1 and the planes z = -1 and z = Z are zero.  Layout
+//   [Z+2][Y][2][nw] uint32 (spin words then occupancy words).
 //
 // Neighbours of the site at row (y, z), column j (p = (y+z) & 1, delta = -1
 // if p == 0 else +1, columns mod W): rows (y+-1, z) and (y, z+-1) at columns
@@ -91,7 +92,7 @@ struct alignas(256) SweepPos {
 
 // Everything a kernel needs to work on one film.
 struct LatDev {
-    uint8_t *spins;       // INT8: [Z+2][Y][W] bytes; BITPACK: [Z+2][Y][2][W/32] words
+    uint8_t *spins;       // INT8: [Z+2][Y][W] bytes; BITPACK: [Z+2][Y][2][ceil(W/32)] words
     DevState *st;
     Slot *slots;          // [kSlots]
     StepDesc *steps;      // [max_steps]
@@ -100,7 +101,7 @@ struct LatDev {
     isf_record *records;  // [max_steps]
     uint32_t X, Y, Z;
     uint32_t W;           // compact sites per row = X/2
-    uint32_t nd;          // INT8: dwords per row = W/4; BITPACK: words per row = W/32
+    uint32_t nd;          // INT8: dwords per row = W/4; BITPACK: words per row = ceil(W/32)
     uint32_t key0, key1;
     uint32_t replica;
     uint32_t format;

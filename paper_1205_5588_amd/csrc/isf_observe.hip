@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_surface_bp(const uint32_t *__restrict__
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= X)
         return;
-    const uint32_t nw = X / 64, j = x >> 1, w = j >> 5, bit = j & 31u;
+    const uint32_t nw = (X / 2 + 31) / 32, j = x >> 1, w = j >> 5, bit = j & 31u;
     int8_t v = 0;
     for (int z = (int)Z - 1 - (int)((Z - 1 + x + y) & 1u); z >= 0; z -= 2) {
         const uint32_t *row = words + ((size_t)(z + 1) * Y + y) * 2 * nw;  // spin words, then occupancy words

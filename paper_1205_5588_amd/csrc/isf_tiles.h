@@ -253,9 +253,14 @@ __device__ __forceinline__ bool phase_block_i8(const LatDev &L, uint32_t sigma, 
 // ---------------------------------------------------------------------------
 // BITPACK format (spin bit + occupancy bit per site)
 
-// Column j of a row shifted by delta: bit i of the result is column 32w+i+delta.
-__device__ __forceinline__ uint32_t shift_bits(bool left, uint32_t cur, uint32_t other) {
-    return left ? ((cur << 1) | (other >> 31)) : ((cur >> 1) | (other << 31));
+// Word w of a row shifted by one column: bit i of the result is column
+// 32w + i - 1 (left) or 32w + i + 1 (right), columns mod W.  other is the
+// neighbouring word in that direction (w - 1 or w + 1, wrapping), and eb the
+// bit where the column from it enters: 31 between whole words; at the row's
+// seam (left of word 0, right of the last word) r - 1, r = the number of
+// columns in the last word, whose bits past r - 1 are zero.
+__device__ __forceinline__ uint32_t shift_bits(bool left, uint32_t cur, uint32_t other, uint32_t eb) {
+    return left ? ((cur << 1) | ((other >> eb) & 1u)) : ((cur >> 1) | ((other & 1u) << eb));
 }
 
 // 4-bit bit-sliced counter: add one bit per site (counts stay <= 12).
@@ -277,12 +282,14 @@ struct NbBits {
     Cnt4 up, vac;
 };
 
-// Neighbour counts of the 32 sites in word w of row (y, z).
-__device__ __forceinline__ NbBits gather_bp(const uint32_t *P, uint32_t Y, uint32_t nw, uint32_t y, uint32_t z,
-                                            uint32_t w, bool left) {
+// Neighbour counts of the 32 sites in word w of row (y, z); W columns per row.
+__device__ __forceinline__ NbBits gather_bp(const uint32_t *P, uint32_t Y, uint32_t nw, uint32_t W, uint32_t y,
+                                            uint32_t z, uint32_t w, bool left) {
     const uint32_t ym = y == 0 ? Y - 1 : y - 1;
     const uint32_t yp = y + 1 == Y ? 0 : y + 1;
     const uint32_t wo = left ? (w == 0 ? nw - 1 : w - 1) : (w + 1 == nw ? 0 : w + 1);
+    const bool seam = left ? w == 0 : w + 1 == nw;
+    const uint32_t eb = seam ? W - 32u * (nw - 1u) - 1u : 31u;
     const size_t p0 = (size_t)z * Y, p1 = p0 + Y, p2 = p1 + Y;
     auto row = [&](size_t plane, uint32_t yy) { return P + (plane + yy) * 2 * nw; };
     NbBits r;
@@ -297,8 +304,8 @@ __device__ __forceinline__ NbBits gather_bp(const uint32_t *P, uint32_t Y, uint3
         const uint32_t s = q[w], so = q[wo], o = q[nw + w], oo = q[nw + wo];
         r.up.add(s);
         r.vac.add(~o);
-        r.up.add(shift_bits(left, s, so));
-        r.vac.add(~shift_bits(left, o, oo));
+        r.up.add(shift_bits(left, s, so, eb));
+        r.vac.add(~shift_bits(left, o, oo, eb));
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -369,12 +376,13 @@ __device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma,
         if (yi >= half)
             break;
         const uint32_t y = 2 * yi + py;
-        const NbBits nb = gather_bp(P, Y, nw, y, z, w, left);
+        const NbBits nb = gather_bp(P, Y, nw, L.W, y, z, w, left);
         if (!nb.occ)
             continue;
         const Idx6 ix = table_index(nb.up, nb.vac, nb.spin);
         // Philox groups: compact index k = (z Y + y) W + 32 w + i, group k >> 2
-        const uint32_t g0 = ((z * Y + y) * nw + w) * 8u;
+        // (W is a multiple of 4: the INT8 format's dword index of the same sites)
+        const uint32_t g0 = (z * Y + y) * (L.W / 4u) + 8u * w;
         uint32_t F = 0;
 #pragma unroll
         for (int g = 0; g < 8; ++g) {

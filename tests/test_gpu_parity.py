@@ -55,10 +55,9 @@ def _assert_same(g, o, what=""):
     assert (ob["M"], ob["E"], ob["n_occ"], ob["n_bonds"], ob["sweeps"]) == st, (what, ob, st)
 
 
-@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("fmt,X", [(0, 72), (1, 128), (1, 72)])
 @pytest.mark.parametrize("init", [0, 1, 2])
-def test_start_state(isf, fmt, init):
-    X = 128 if fmt else 72
+def test_start_state(isf, fmt, X, init):
     h = _rand_h((38, X), 5, 1 + init)
     g, o = _pair(isf, h, 5, 0xDEADBEEF12345, replica=7, init=init, fmt=fmt)
     _say("start", fmt, init)
@@ -104,6 +103,34 @@ def test_bitpack_matches_oracle(isf, tiling):
     steps = [(2.0, 25, 4, 0), (6.0, -13, 3, 1), (0.5, 0, 3, 0)]
     np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
     _assert_same(g, o)
+
+
+# bit-packed rows that end in a partly filled word (W = X/2 sites, W mod 32 = r):
+# the periodic seam takes its column from bit r - 1 of the last word
+BP_PARTIAL = [(8, 4, 2), (72, 10, 3), (88, 26, 4), (120, 12, 5), (1000, 6, 2)]
+
+
+@pytest.mark.parametrize("tiling", [(64, 4, 1), (32, 8, 2), (16, 16, 1)])
+@pytest.mark.parametrize("X,Y,Z", BP_PARTIAL)
+def test_bitpack_partial_words_match_oracle_and_int8(isf, tiling, X, Y, Z):
+    h = _rand_h((Y, X), Z, 3 * X + Y)
+    g, o = _pair(isf, h, Z, 8642, replica=5, init=2, fmt=1, tuning=tiling + (X % 16 == 8,))
+    _say("bitpack partial words", X, Y, Z, tiling)
+    steps = [(2.0, 25, 5, 0), (6.0, -13, 3, 1), (3.0, 30, 4, 0, 40), (0.5, 0, 3, 0)]
+    rg = g.run_schedule(steps)
+    np.testing.assert_array_equal(rg, np.array([o.run(*st).as_tuple() for st in steps]))
+    _assert_same(g, o)
+    i8 = isf.Lattice(h, Z, 8642, replica=5, init=2)
+    np.testing.assert_array_equal(i8.run_schedule(steps), rg)
+    np.testing.assert_array_equal(i8.spins(), g.spins())
+    # a state written back and read again, then more sweeps from it
+    cube = g.spins()
+    cube[:, 0, :] = np.where(cube[:, 0, :] != 0, -cube[:, 0, :], 0)
+    g.set_spins(cube, 100)
+    o.set_spins(cube, 100)
+    _assert_same(g, o, "written")
+    np.testing.assert_array_equal(g.run_sweeps(4.0, -20, 3), o.run(4.0, -20, 3).as_tuple())
+    _assert_same(g, o, "after writing")
 
 
 def test_graph_replay_matches_plain(isf):
@@ -278,9 +305,8 @@ def test_batched_equals_alone_and_oracle(isf, mode, fmt):
     if mode == 2 and fmt == 1:
         pytest.skip("whole-sweep batches take INT8 films (rejection tested separately)")
     films = _batch_films(isf)
-    if fmt == 1:
-        films = [(np.tile(h, (1, 2))[:, : max(64, (h.shape[1] // 64) * 64)], Z, s, r, sc)
-                 for (h, Z, s, r, sc) in films]
+    if fmt == 1:  # 8 columns narrower: bit-packed rows that end in a partly filled word
+        films = [(h[:, : h.shape[1] - 8], Z, s, r, sc) for (h, Z, s, r, sc) in films]
     _say("batch mode", mode, "fmt", fmt)
     lats = [isf.Lattice(h, Z, s, replica=r, init=2, fmt=fmt) for (h, Z, s, r, sc) in films]
     b = isf.Batch(len(lats))
@@ -726,9 +752,10 @@ def test_gated_bitpacked_batch_equals_oracle(isf, mode):
 
 # ------------------------------------------------------------------ PMOKE image and film statistics
 @pytest.mark.parametrize("fmt,kernel,tiling", [(0, 0, (64, 4, 2)), (0, 2, (32, 16, 8)), (1, 0, (64, 4, 1)),
-                                               (0, 3, (32, 16, 16))])
+                                               (0, 3, (32, 16, 16)), (1, 0, (32, 8, 2))])
 def test_surface_image_matches_oracle(isf, fmt, kernel, tiling):
-    X = 256 if fmt else (352 if kernel == 3 else 200)
+    # the second bit-packed case has rows of 100 sites: three whole words and one of 4 sites
+    X = (256 if tiling[0] == 64 else 200) if fmt else (352 if kernel == 3 else 200)
     h = _rand_h((58, X), 6, 40 + fmt + kernel)
     g, o = _pair(isf, h, 6, 1357, replica=2, init=2, fmt=fmt)
     g.set_tuning(tiling[0], tiling[1], tiling[2], False, kernel)

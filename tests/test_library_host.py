@@ -59,7 +59,10 @@ def test_descriptor_validation(lib):
     assert rc == 0 and s == 10 * 2048 * 2 * 32 * 4
     for bad in [(4, 8, 2), (12, 8, 2), (16, 6, 0), (16, 7, 2), (16, 2, 2), (16, 8, 65)]:
         assert _bytes(lib, *bad)[0] == -1, bad
-    assert _bytes(lib, 32, 8, 2, fmt=1)[0] == -1      # BITPACK needs X % 64 == 0
+    assert _bytes(lib, 12, 8, 2, fmt=1)[0] == -1      # BITPACK too needs X % 8 == 0
+    # BITPACK rows of W = X/2 sites take ceil(W/32) words per bit plane: X = 72 -> 36 sites -> 2 words
+    rc, s, _ = _bytes(lib, 72, 8, 2, fmt=1)
+    assert rc == 0 and s == 4 * 8 * 2 * 2 * 4
     assert _bytes(lib, 64, 8, 2, fmt=2)[0] == -1      # unknown format
     assert _bytes(lib, 64, 8, 2, reserved=1)[0] == -1
     assert b"Z=65" in lib.isf_last_error() or b"reserved" in lib.isf_last_error()
