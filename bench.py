@@ -156,7 +156,8 @@ def roofline_int8(lat, cfg, steps, region_ms_per_sweep):
         mean_ms, bytes_per_launch, min_bytes = sum(ms) / 4.0, 1.25 * Nc, 0.5 * Nc
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
     kernel = lat_kernel_name(lat)
-    traffic = measured_traffic(kernel)
+    trec = measured_traffic(kernel)
+    traffic = int(trec["fetch_bytes_per_launch"] + trec["write_bytes_per_launch"]) if trec else None
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
            "kernel": kernel, "ms_per_launch": round(mean_ms, 5),
@@ -169,6 +170,7 @@ def roofline_int8(lat, cfg, steps, region_ms_per_sweep):
            "limiter": "integer VALU + LDS latency; film resident in the Infinity Cache"}
     if traffic:
         out["traffic_frac"] = round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out["traffic_window"] = trec.get("window")
     return out
 
 
@@ -190,9 +192,9 @@ KERNEL_SOURCES = ("isf_sweep.hip", "isf_device.h", "isf_internal.h")
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
-    known size) from the committed counter summary, or None when there is none or
-    the kernel's sources changed since the counters were taken."""
+    """The committed counter record of `kernel` (FETCH_SIZE and WRITE_SIZE bytes per
+    launch, scaled by a copy of known size, and the launches they were taken over),
+    or None when there is none or the kernel's sources changed since."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -206,7 +208,7 @@ def measured_traffic(kernel):
     blob = b"".join(open(os.path.join(csrc, n), "rb").read() for n in KERNEL_SOURCES)
     if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
         return None
-    return int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
+    return rec
 
 
 def lat_kernel_name(lat):
@@ -477,6 +479,8 @@ def run_only(args, cfg, h):
         tl, kern = tl[:3], tl[3]
     if args.only == "batched":
         return bench_batched(args)
+    if args.only == "plain":
+        return run_plain_untimed(args, cfg, h)
     if args.only == "bitpack":
         if tl is None and not args.no_tune:
             tb = tune_plain(cfg, h, 1)
@@ -487,6 +491,28 @@ def run_only(args, cfg, h):
     if tl is None:
         tl, kern = (32, 32, 16), KERNEL_PIPE
     return bench_aniso(cfg, h, args.steps, tl + (True, kern))
+
+
+def run_plain_untimed(args, cfg, h):
+    """The plain ramp's first --steps field steps (after one warm-up step) in the
+    launch shape of --plain-tiling (default: the pipelined kernel, 32 x 32 tiles, graph
+    replay), with no timing of any kind: the workload of the rocprofv3 counter passes."""
+    import numpy as np
+
+    from paper_1205_5588_amd.lattice import Lattice
+
+    tl = (tuple(int(v) for v in args.plain_tiling.split(",")) if args.plain_tiling
+          else (32, 32, 16, KERNEL_PIPE, 1))
+    lat = Lattice(h, cfg.Z, cfg.mc_seed, init=cfg.init)
+    lat.set_tuning(tl[0], tl[1], tl[2], bool(tl[4]), tl[3])
+    sps = cfg.sweeps_per_step
+    lat.run_schedule([(cfg.T, cfg.h_nums[0], sps, 0)])
+    steps = [(cfg.T, hv, sps, 0) for hv in cfg.h_nums[: args.steps]]
+    rec = lat.run_schedule(steps)
+    out = {"kernel": lat_kernel_name(lat), "tiling": list(lat.get_tuning()), "sweeps": len(steps) * sps,
+           "warmup_sweeps": sps, "accepted": int(np.asarray(rec)[:, 5].sum())}
+    lat.close()
+    return out
 
 
 def bench_aniso(cfg, h, k, tuning):
@@ -522,8 +548,10 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched"], default=None,
-                    help="run only this one of the extra measurements and print its result (for profiling)")
+    ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched", "plain"], default=None,
+                    help="run only this one of the extra measurements and print its result (for profiling); "
+                         "plain: the first --steps field steps of the plain ramp and nothing else, untimed "
+                         "(no events between launches), for counter passes")
     ap.add_argument("--plain-tiling", default=None,
                     help="the plain ramp's launch shape tx,ty,rows,kernel,graph instead of the tuner's (graph 0: "
                          "plain launches, e.g. for counter passes that need no graph replay)")
