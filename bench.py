@@ -326,15 +326,19 @@ def serving_inputs(args, rate=50.0, duration=None):
     return reqs, {q.rid: hh for q, hh in zip(reqs, heights)}
 
 
-def bench_serving(args, reqs, hmap, rate=50.0, duration=None):
+def bench_serving(args, reqs, hmap, rate=50.0, duration=None, shape=None):
     """Poisson arrivals (50 req/s for the configured duration) of hysteresis and
-    temperature-scan jobs on films of 64^2..2048^2 x 1..10 layers."""
+    temperature-scan jobs on films of 64^2..2048^2 x 1..10 layers.  shape: (format,
+    sublattice tiling) for every request, e.g. the batch tuner's pick for the
+    batched workload (default: int8 films in their own default shapes)."""
     duration = duration or args.serve_duration
     from paper_1205_5588_amd.serve import GpuExecutor, Job, Server
 
-    jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q), n_sweeps=q.n_sweeps, payload=q)
-            for q in reqs]
-    ex = GpuExecutor(max_slots=args.serve_slots, mode=args.serve_mode, heights_of=lambda q: hmap[q.rid])
+    fmt, tiling = shape if shape else (0, None)
+    jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q, fmt), n_sweeps=q.n_sweeps,
+                payload=q) for q in reqs]
+    ex = GpuExecutor(max_slots=args.serve_slots, mode=args.serve_mode, heights_of=lambda q: hmap[q.rid],
+                     tiling=tuple(tiling) + (False, 0) if tiling else None, fmt=fmt)
     srv = Server(ex, budget_bytes=int(args.serve_budget_gib * 2**30), max_slots=args.serve_slots,
                  target_chunk_s=0.02, rate_estimate=2e11, max_chunk=64)
     t0 = time.perf_counter()
@@ -351,6 +355,8 @@ def bench_serving(args, reqs, hmap, rate=50.0, duration=None):
     s["wall_s"] = round(wall, 2)
     s["offered_attempts_per_s"] = round(s["attempts"] / duration, 1)
     s["mode"] = {0: "phase_launch", 1: "persistent", 2: "whole_sweep", 3: "pipelined"}[args.serve_mode]
+    s["format"] = {0: "int8", 1: "bitpack"}[fmt]
+    s["tiling"] = list(tiling) if tiling else "each film's default"
     s["arrivals"] = "Poisson %g req/s for %g s" % (rate, duration)
     return s
 
@@ -646,13 +652,19 @@ def main():
         extra["batched"] = bench_batched(args)
         log("batched:", {k: v for k, v in extra["batched"].items() if k != "tuning"})
         if not args.no_serve:
-            extra["serving"] = bench_serving(args, *serving_inputs(args))
+            # requests take the format and sublattice shape the batch tuner picked for the
+            # batched workload (films of the same kind) when both run one launch per sublattice
+            bt = extra["batched"]
+            shape = None
+            if args.serve_mode == 0 and bt["mode"] == "phase_launch":
+                shape = (0 if bt["format"] == "int8" else 1, bt["tiling"])
+            extra["serving"] = bench_serving(args, *serving_inputs(args), shape=shape)
             log("serving:", extra["serving"])
             # the same request mix at 15 req/s for 30 s, below the GPU's capacity, where
             # the latency is service time rather than backlog
             d = min(30.0, args.serve_duration)
             extra["serving_below_capacity"] = bench_serving(args, *serving_inputs(args, 15.0, d), rate=15.0,
-                                                            duration=d)
+                                                            duration=d, shape=shape)
             log("serving below capacity:", extra["serving_below_capacity"])
 
     cpu_base = None

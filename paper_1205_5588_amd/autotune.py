@@ -151,9 +151,14 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
 
 # (tile_x, tile_y, rows or waves, batch mode); in the pipelined mode the shape is
 # that of the films the pipelined kernel cannot take (sublattice launches)
-BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH), (64, 4, 2, BATCH_PERSISTENT),
-                    (16, 16, 4, BATCH_WHOLE), (32, 8, 4, BATCH_WHOLE), (32, 16, 8, BATCH_WHOLE),
-                    (64, 4, 2, BATCH_PIPE), (32, 8, 2, BATCH_PIPE)]
+# Sublattice shapes of both formats (a shape the format does not compile is
+# refused and skipped): on batches of small films the narrow bit-packed tiles
+# (16 words, 512 sites per row of a tile) and the int8 tiles with four rows per
+# thread lead.
+BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (64, 4, 4, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH),
+                    (32, 8, 4, BATCH_PHASE_LAUNCH), (16, 16, 1, BATCH_PHASE_LAUNCH), (16, 16, 2, BATCH_PHASE_LAUNCH),
+                    (64, 4, 2, BATCH_PERSISTENT), (16, 16, 4, BATCH_WHOLE), (32, 8, 4, BATCH_WHOLE),
+                    (32, 16, 8, BATCH_WHOLE), (64, 4, 2, BATCH_PIPE), (32, 8, 2, BATCH_PIPE)]
 
 
 def tune_batch(make_lats: Callable[..., list], schedule_of: Callable[[int], list], fmt: int,

@@ -126,3 +126,27 @@ def test_serving_alone_equals_in_mix(isf, mode):
         np.testing.assert_array_equal(np.array([o.run(*s).as_tuple() for s in request_schedule(q)]), res.records)
     s = stats.summary()
     assert s["p99_s"] >= s["p50_s"] > 0
+
+
+@pytest.mark.parametrize("fmt,tiling", [(1, (16, 16, 1)), (0, (64, 4, 4))])
+def test_serving_in_a_tuned_shape_equals_alone(isf, fmt, tiling):
+    """Requests served as bit-packed films in narrow tiles (or int8 films with four rows per
+    thread), the shapes the batch tuner picks for batches of small films: the same records
+    as each request alone as an int8 film in its default shape, and as the oracle."""
+    from paper_1205_5588_amd.serve import GpuExecutor, Job, Server, request_schedule
+
+    reqs = _small_requests()
+    jobs = [Job(rid=q.rid, arrival=q.arrival, footprint=GpuExecutor.footprint(q, fmt), n_sweeps=q.n_sweeps,
+                payload=q) for q in reqs]
+    _say("serving in shape", fmt, tiling)
+    srv = Server(GpuExecutor(max_slots=4, mode=0, tiling=tiling + (False, 0), fmt=fmt), budget_bytes=10**9,
+                 max_slots=4, target_chunk_s=0.001, rate_estimate=1e10, max_chunk=16)
+    stats = srv.run(jobs)
+    assert len(stats.results) == len(reqs)
+    for q, res in zip(reqs, stats.results):
+        alone = isf.Lattice(q.heights(), q.Z, q.seed, replica=0, init=q.init)
+        np.testing.assert_array_equal(alone.run_schedule(request_schedule(q)), res.records,
+                                      err_msg="request %d" % q.rid)
+    q, res = reqs[0], stats.results[0]
+    o = cpu.Film(q.heights(), q.Z, q.seed, 0, init=q.init)
+    np.testing.assert_array_equal(np.array([o.run(*s).as_tuple() for s in request_schedule(q)]), res.records)
