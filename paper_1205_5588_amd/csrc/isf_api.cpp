@@ -1726,6 +1726,11 @@ int32_t isf_batch_create(uint32_t max_lats, void *ws, uint64_t ws_bytes, void *s
                     (unsigned long long)need);
     if ((uintptr_t)ws & 255)
         return fail(ISF_EINVAL, "workspace must be 256-byte aligned");
+    // the current device, made current explicitly: a batch may be the first
+    // object a process creates, before anything else has touched the runtime
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipSetDevice(dev) != hipSuccess)
+        return fail(ISF_EHIP, "no usable HIP device");
     isf_batch *b = new (std::nothrow) isf_batch();
     if (!b)
         return fail(ISF_EINVAL, "out of host memory");

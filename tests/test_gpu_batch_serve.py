@@ -3,6 +3,7 @@ sublattice or one persistent launch) and the serving loop (continuous
 batching) give every replica / request exactly the trajectory it has alone,
 and sampled replicas match the CPU oracle."""
 
+import os
 import sys
 
 import numpy as np
@@ -150,3 +151,23 @@ def test_serving_in_a_tuned_shape_equals_alone(isf, fmt, tiling):
     q, res = reqs[0], stats.results[0]
     o = cpu.Film(q.heights(), q.Z, q.seed, 0, init=q.init)
     np.testing.assert_array_equal(np.array([o.run(*s).as_tuple() for s in request_schedule(q)]), res.records)
+
+
+def test_batch_as_first_object_of_a_process(isf):
+    """A batch context created before any lattice in a fresh process (a server's
+    first action) gets a usable device and advances a lattice created after it."""
+    import subprocess
+
+    code = ("import numpy as np, torch\n"
+            "from paper_1205_5588_amd.lattice import Batch, Lattice\n"
+            "b = Batch(64)\n"
+            "h = np.random.default_rng(1).integers(0, 4, size=(64, 64)).astype(np.uint8)\n"
+            "lat = Lattice(h, 3, 7, init=2)\n"
+            "lat.schedule_load([(3.0, 10, 5, 0)])\n"
+            "b.advance([lat], 5)\n"
+            "b.sync()\n"
+            "print(lat.observables()['sweeps'])\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "5"
