@@ -54,12 +54,15 @@ def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
     """Heuristic (tile_x, tile_y, rows_or_waves, use_graph, kernel) for films not in the cache.
 
     INT8 films whose planes fit a whole-sweep kernel's LDS take one (measured
-    fastest on MI355X: the pipelined 32 x 32 kernel on wide films such as
-    2048^2 x 8, the single-tile kernel with 16 x 16 tiles on small films such
-    as 512^2 x 5); others take the sublattice tiles."""
+    fastest on MI355X: the pipelined kernel with 32 x 32 tiles on wide films
+    such as 2048^2 x 8, with 32 x 8 tiles on medium films such as 512^2 x 5, the
+    single-tile kernel with 16 x 16 tiles on films too small for the pipelined
+    one's region); others take the sublattice tiles."""
     if fmt == FORMAT_INT8 and Z <= 8:
         if X // 8 >= 256 and Y >= 512:
             return (32, 32, 16, True, KERNEL_PIPE)
+        if X // 8 >= 40 and Y >= 16:
+            return (32, 8, 8, True, KERNEL_PIPE)
         return (16, 16, 4, True, KERNEL_SWEEP)
     return default_tiling(X, fmt) + (True, KERNEL_TILES)
 
@@ -98,7 +101,7 @@ SWEEP_CANDIDATES = [(32, 16, 8, KERNEL_SWEEP), (16, 16, 4, KERNEL_SWEEP), (32, 8
                     (64, 8, 8, KERNEL_SWEEP), (32, 32, 8, KERNEL_SWEEP), (32, 32, 16, KERNEL_SWEEP)]
 # pipelined whole-sweep kernel (one block per compute unit, double-buffered LDS)
 PIPE_CANDIDATES = [(32, 16, 16, KERNEL_PIPE), (32, 16, 8, KERNEL_PIPE), (32, 32, 16, KERNEL_PIPE),
-                   (64, 16, 16, KERNEL_PIPE)]
+                   (64, 16, 16, KERNEL_PIPE), (32, 8, 8, KERNEL_PIPE)]
 
 
 def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,

@@ -1618,7 +1618,7 @@ hipError_t launch_sweep_i8_halo_batch(const WholeEntry *ents, const uint32_t *be
     return hipErrorInvalidValue;
 }
 
-#define ISF_PIPE_SHAPES(X) X(32, 16) X(32, 32) X(64, 16)
+#define ISF_PIPE_SHAPES(X) X(32, 8) X(32, 16) X(32, 32) X(64, 16)
 
 // Pipelined whole-sweep kernel: dynamic LDS bytes for a film of Z planes (0 if
 // (tile_x, tile_y) is not a compiled shape), its static LDS, region dwords

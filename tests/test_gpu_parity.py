@@ -515,7 +515,7 @@ def test_sweep_kernel_switches_and_reads_midway(isf):
 PIPE_CASES = [((320, 24, 5), (32, 16, 16)), ((352, 42, 6), (32, 16, 8)), ((576, 40, 9), (32, 16, 16)),
               ((384, 64, 1), (32, 32, 16)), ((352, 72, 8), (32, 32, 8)), ((640, 50, 3), (64, 16, 16)),
               ((1280, 960, 3), (32, 16, 16)), ((320, 32, 14), (32, 16, 16)), ((328, 30, 14), (32, 16, 8)),
-              ((576, 24, 7), (64, 16, 16))]
+              ((576, 24, 7), (64, 16, 16)), ((320, 16, 5), (32, 8, 8)), ((344, 22, 9), (32, 8, 16))]
 
 
 @pytest.mark.parametrize("film,tiling", PIPE_CASES)
@@ -559,7 +559,7 @@ def test_pipe_kernel_rejects_unsupported(isf):
     with pytest.raises(IsfError):
         isf.Lattice(h, 4, 1, fmt=1).set_tuning(32, 16, 16, False, 3)  # bit-packed film
     g = isf.Lattice(h, 4, 1)
-    for bad in ((32, 8, 16), (16, 16, 16), (32, 16, 4), (32, 16, 32)):
+    for bad in ((32, 8, 4), (16, 16, 16), (32, 16, 4), (32, 16, 32), (64, 8, 16)):
         with pytest.raises(IsfError):
             g.set_tuning(bad[0], bad[1], bad[2], False, 3)
     for hh, Z in ((_rand_h((64, 256), 4, 3), 4),  # narrower than one 32 x 16 region (40 dwords)
