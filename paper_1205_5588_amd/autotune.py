@@ -54,15 +54,14 @@ def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
     """Heuristic (tile_x, tile_y, rows_or_waves, use_graph, kernel) for films not in the cache.
 
     INT8 films whose planes fit a whole-sweep kernel's LDS take one (measured
-    fastest on MI355X: the pipelined kernel with 32 x 32 tiles on wide films
-    such as 2048^2 x 8, with 32 x 8 tiles on medium films such as 512^2 x 5, the
-    single-tile kernel with 16 x 16 tiles on films too small for the pipelined
-    one's region); others take the sublattice tiles."""
+    on MI355X: the pipelined kernel with 32 x 32 tiles on wide films such as
+    2048^2 x 8; the single-tile kernel with 16 x 16 tiles on smaller films,
+    where the pipelined kernel's 32 x 8 tiles win on some (512^2 x 5 at T up to
+    12) and lose on others (the batched workload's films, hot replicas among
+    them), so the tuner decides); others take the sublattice tiles."""
     if fmt == FORMAT_INT8 and Z <= 8:
         if X // 8 >= 256 and Y >= 512:
             return (32, 32, 16, True, KERNEL_PIPE)
-        if X // 8 >= 40 and Y >= 16:
-            return (32, 8, 8, True, KERNEL_PIPE)
         return (16, 16, 4, True, KERNEL_SWEEP)
     return default_tiling(X, fmt) + (True, KERNEL_TILES)
 
