@@ -30,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_LIST, KERNEL_SWEEP, KERNEL_PIPE = 1, 2, 3  # isf_tuning.kernel
+KERNEL_LIST, KERNEL_SWEEP, KERNEL_PIPE, KERNEL_FILM = 1, 2, 3, 4  # isf_tuning.kernel
 
 
 def log(*a):
@@ -214,7 +214,7 @@ def measured_traffic(kernel):
 def lat_kernel_name(lat):
     t = lat.get_tuning()
     return {KERNEL_LIST: "k_phase_i8_list", KERNEL_SWEEP: "k_sweep_i8_halo",
-            KERNEL_PIPE: "k_sweep_i8_pipe"}.get(t[4], "k_phase_i8")
+            KERNEL_PIPE: "k_sweep_i8_pipe", KERNEL_FILM: "k_sweep_i8_film"}.get(t[4], "k_phase_i8")
 
 
 def bench_surface_image(lat, cfg, reps=20):
@@ -363,8 +363,8 @@ def bench_serving(args, reqs, hmap, rate=50.0, duration=None, shape=None):
 
 def bench_small_configs(tune=True):
     """The two other plain workloads, whole, with HIP events around each: the small
-    ramp (64x64x3, 161 field steps x 100 sweeps, launch- and latency-bound: a
-    6 KiB film, so no roofline) and the temperature scan (512x512x5, 45
+    ramp (64x64x3, 161 field steps x 100 sweeps: a 6 KiB film that the film
+    kernel sweeps from one compute unit's LDS, latency-bound, so no roofline) and the temperature scan (512x512x5, 45
     temperatures x 1000 sweeps, the first 200 of each discarded), each in the
     launch shape the tuner picks for it."""
     import torch
@@ -407,7 +407,7 @@ def bench_small_configs(tune=True):
                      "hbm_frac_5Nc": None if name == "small_ramp" else
                      round(5 * (cfg.X * cfg.Y * cfg.Z // 2) / (ms * 1e-3 / sweeps) / 1e9 / HBM_PEAK_GBS, 4)}
         if name == "small_ramp":
-            out[name]["roofline"] = "n/a: launch- and latency-bound"
+            out[name]["roofline"] = "n/a: one compute unit, latency-bound"
         del lat
     return out
 
@@ -487,6 +487,8 @@ def run_only(args, cfg, h):
         return bench_batched(args)
     if args.only == "plain":
         return run_plain_untimed(args, cfg, h)
+    if args.only == "small":
+        return bench_small_configs(tune=not args.no_tune)
     if args.only == "bitpack":
         if tl is None and not args.no_tune:
             tb = tune_plain(cfg, h, 1)
@@ -554,10 +556,11 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched", "plain"], default=None,
+    ap.add_argument("--only", choices=["bitpack", "anisotropy", "batched", "plain", "small"], default=None,
                     help="run only this one of the extra measurements and print its result (for profiling); "
                          "plain: the first --steps field steps of the plain ramp and nothing else, untimed "
-                         "(no events between launches), for counter passes")
+                         "(no events between launches), for counter passes; small: the small ramp and the "
+                         "temperature scan")
     ap.add_argument("--plain-tiling", default=None,
                     help="the plain ramp's launch shape tx,ty,rows,kernel,graph instead of the tuner's (graph 0: "
                          "plain launches, e.g. for counter passes that need no graph replay)")

@@ -124,7 +124,7 @@ typedef struct {
 } isf_obs;
 
 /* Launch shape of the sweep kernels.  Every shape gives the same trajectory. */
-enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1, ISF_KERNEL_SWEEP = 2, ISF_KERNEL_PIPE = 3 };
+enum { ISF_KERNEL_TILES = 0, ISF_KERNEL_LIST = 1, ISF_KERNEL_SWEEP = 2, ISF_KERNEL_PIPE = 3, ISF_KERNEL_FILM = 4 };
 typedef struct {
     uint32_t tile_x;    /* dwords (4 sites) per block row: 16, 32 or 64 */
     uint32_t tile_y;    /* TILES/LIST: active rows per block, tile_x * tile_y = 256;
@@ -139,7 +139,11 @@ typedef struct {
                            (INT8: one launch per sweep, one block per compute unit sweeping several tiles while
                            the next tile's region streams into a second LDS buffer; EINVAL unless X is a
                            multiple of 32, X/8 and Y are at least the region's width and height, and the
-                           double buffer fits the device's LDS) */
+                           double buffer fits the device's LDS); ISF_KERNEL_FILM (INT8, tile_x 512, tile_y 1,
+                           rows_per_thread 1: one block holds the whole film in LDS and runs many sweeps per
+                           launch, the books of each sweep included; EINVAL unless the film's (Z+2) Y X/8
+                           dwords are at most 65536 and fit the block's LDS with the sublattice lists, and for
+                           a schedule with the anisotropy term; no graphs, no launch timing) */
 } isf_tuning;
 
 typedef struct isf_lattice isf_lattice;

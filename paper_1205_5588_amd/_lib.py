@@ -56,7 +56,7 @@ class Tuning(ctypes.Structure):
                 ("use_graph", ctypes.c_uint32), ("kernel", ctypes.c_uint32)]
 
 
-KERNEL_TILES, KERNEL_LIST, KERNEL_SWEEP, KERNEL_PIPE = 0, 1, 2, 3
+KERNEL_TILES, KERNEL_LIST, KERNEL_SWEEP, KERNEL_PIPE, KERNEL_FILM = 0, 1, 2, 3, 4
 
 
 EXPORTS = {

@@ -21,8 +21,7 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from ._lib import (BATCH_PERSISTENT, BATCH_PHASE_LAUNCH, BATCH_PIPE, BATCH_WHOLE, FORMAT_BITPACK, FORMAT_INT8,
-                   KERNEL_LIST,
-                   KERNEL_PIPE, KERNEL_SWEEP, KERNEL_TILES, IsfError)
+                   KERNEL_FILM, KERNEL_LIST, KERNEL_PIPE, KERNEL_SWEEP, KERNEL_TILES, IsfError)
 
 TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
@@ -101,6 +100,8 @@ SWEEP_CANDIDATES = [(32, 16, 8, KERNEL_SWEEP), (16, 16, 4, KERNEL_SWEEP), (32, 8
 # pipelined whole-sweep kernel (one block per compute unit, double-buffered LDS)
 PIPE_CANDIDATES = [(32, 16, 16, KERNEL_PIPE), (32, 16, 8, KERNEL_PIPE), (32, 32, 16, KERNEL_PIPE),
                    (64, 16, 16, KERNEL_PIPE), (32, 8, 8, KERNEL_PIPE)]
+# the whole film in one block's LDS, many sweeps per launch (films that fit it)
+FILM_CANDIDATES = [(512, 1, 1, KERNEL_FILM)]
 
 
 def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, sweeps: int = 64,
@@ -115,7 +116,7 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
 
     cands = [tuple(c) + ((KERNEL_TILES,) if len(c) == 3 else ()) for c in (candidates or TILINGS[fmt])]
     if fmt == FORMAT_INT8 and candidates is None:
-        cands += (LIST_CANDIDATES if lists else []) + SWEEP_CANDIDATES + PIPE_CANDIDATES
+        cands += (LIST_CANDIDATES if lists else []) + SWEEP_CANDIDATES + PIPE_CANDIDATES + FILM_CANDIDATES
     ref_recs = ref_spins = None
     timings: List[dict] = []
     for tl in cands:

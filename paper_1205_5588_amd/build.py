@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libisf.so")
-SOURCES = ["isf_api.cpp", "isf_kernels.hip", "isf_bitpack.hip", "isf_persistent.hip", "isf_sweep.hip", "isf_observe.hip", "isf_ceiling.hip"]
+SOURCES = ["isf_api.cpp", "isf_kernels.hip", "isf_bitpack.hip", "isf_persistent.hip", "isf_sweep.hip", "isf_observe.hip",
+           "isf_ceiling.hip", "isf_film.hip"]
 ARCH = os.environ.get("ISF_OFFLOAD_ARCH", "gfx950")
 
 

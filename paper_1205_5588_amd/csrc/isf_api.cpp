@@ -52,6 +52,8 @@ hipError_t launch_pipe_lists(const LatDev &L, const Tiling &tl, uint8_t *lists, 
 hipError_t launch_sweep_i8_pipe(const LatDev &L, const Tiling &tl, const uint8_t *src, uint8_t *dst,
                                 uint8_t *lists, uint32_t q, uint32_t n_cu, hipStream_t s);
 hipError_t launch_pipe_reset(const LatDev &L, const Tiling &tl, uint8_t *lists, hipStream_t s);
+uint32_t film_lds_bytes(uint32_t Y, uint32_t Z, uint32_t nd, uint32_t max_lds);
+hipError_t launch_sweep_i8_film(const LatDev &L, uint32_t n_sweeps, uint32_t lds, hipStream_t s);
 uint32_t halo_lds_bytes(uint32_t tx, uint32_t ty, uint32_t Z);
 uint32_t halo_region_dwords(uint32_t tx, uint32_t ty, uint32_t Z);
 uint64_t halo_lists_bytes(uint32_t tx, uint32_t ty, uint32_t nd, uint32_t Y, uint32_t Z);
@@ -492,8 +494,32 @@ int32_t build_tail_graph(isf_lattice *lat, uint32_t sweeps) {
     return ISF_OK;
 }
 
+// The film kernel: one block, many sweeps per launch (at most kFilmChunk each).
+constexpr uint64_t kFilmChunk = 4096;
+
+int32_t enqueue_sweeps_film(isf_lattice *lat, uint64_t n) {
+    int32_t rc;
+    if ((rc = settle(lat)))
+        return rc;
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
+    const uint32_t lds = film_lds_bytes(lat->d.Y, lat->d.Z, lat->L.nd, (uint32_t)max_lds);
+    if (!lds)
+        return fail(ISF_EINVAL, "the film does not fit one block's LDS");
+    while (n > 0) {
+        const uint64_t k = std::min(n, kFilmChunk);
+        hipError_t e = launch_sweep_i8_film(lat->L, (uint32_t)k, lds, lat->stream);
+        if (e != hipSuccess)
+            return fail(ISF_EHIP, "film kernel launch failed: %s", hipGetErrorString(e));
+        n -= k;
+    }
+    return ISF_OK;
+}
+
 int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     int32_t rc0;
+    if (lat->tiling.kernel == ISF_KERNEL_FILM)
+        return enqueue_sweeps_film(lat, n);
     if (is_whole(lat->tiling.kernel)) {
         if ((rc0 = prepare_spare(lat, lat->tiling)) || (rc0 = prime_whole(lat)))
             return rc0;
@@ -1007,6 +1033,18 @@ int32_t isf_set_tuning(isf_lattice *lat, const isf_tuning *t) {
         int32_t rc = pipe_fits(lat, tl, lat->d.Z, false);
         if (rc)
             return rc;
+    } else if (tl.kernel == ISF_KERNEL_FILM) {
+        if (lat->d.format != ISF_FORMAT_INT8)
+            return fail(ISF_EINVAL, "the film kernel needs an INT8 film");
+        if (tl.tx != 512 || tl.ty != 1 || tl.ry != 1)
+            return fail(ISF_EINVAL, "film kernel: tile_x 512, tile_y 1, rows_per_thread 1");
+        int max_lds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, lat->device));
+        if (!film_lds_bytes(lat->d.Y, lat->d.Z, lat->L.nd, (uint32_t)max_lds))
+            return fail(ISF_EINVAL, "film of %u x %u x %u does not fit one block's LDS", lat->d.X, lat->d.Y,
+                        lat->d.Z);
+        if (lat->aniso)
+            return fail(ISF_EINVAL, "the loaded schedule has the anisotropy term, which the film kernel does not take");
     } else if (tl.kernel != ISF_KERNEL_TILES) {
         return fail(ISF_EINVAL, "unknown kernel %u", tl.kernel);
     } else {
@@ -1151,7 +1189,7 @@ int32_t isf_schedule_load(isf_lattice *lat, const isf_step *steps, uint32_t n) {
         if (steps[i].an_num != 0) {
             if (lat->d.format != ISF_FORMAT_INT8)
                 return fail(ISF_EINVAL, "step %u: the anisotropy term needs an INT8 film", i);
-            if (is_whole(lat->tiling.kernel) && !lat->spec_ws)
+            if ((is_whole(lat->tiling.kernel) && !lat->spec_ws) || lat->tiling.kernel == ISF_KERNEL_FILM)
                 return fail(ISF_EINVAL,
                             "step %u: the anisotropy term needs the per-sublattice kernels (tuning kernel TILES "
                             "or LIST), or a workspace for the whole-sweep kernels (isf_attach_aniso_workspace)",
@@ -1453,6 +1491,8 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         return rc;
     if (lat->aniso && is_whole(lat->tiling.kernel))
         return fail(ISF_EINVAL, "launch timing of an anisotropic schedule on a whole-sweep kernel is not supported");
+    if (lat->tiling.kernel == ISF_KERNEL_FILM)
+        return fail(ISF_EINVAL, "the film kernel runs many sweeps per launch: no launch timing");
     const uint32_t n = (uint32_t)std::min<uint64_t>(n_sweeps, lat->sched_total - lat->sched_enqueued);
     // timing-only events: no system-scope fence when they are recorded, so that
     // the pairs measure the launch between them and not a cache write-back

@@ -531,6 +531,95 @@ def test_pipe_kernel_matches_oracle(isf, film, tiling):
     _assert_same(g, o)
 
 
+# ------------------------------------------------------------------ the film kernel (one block, whole film in LDS)
+# sublattices of at most 512 dwords (one per thread: 64 x 64 x 3, 8 x 4 x 1, 136 x 20 x 4, ...) and
+# of more (the listed form: 72 x 38 x 5 with 513, 256 x 128 x 4, 40 x 70 x 13)
+FILM_CASES = [(64, 64, 3), (8, 4, 1), (72, 38, 5), (136, 20, 4), (264, 10, 2), (24, 6, 9), (512, 12, 1),
+              (256, 128, 4), (40, 70, 13), (64, 62, 3)]
+
+
+@pytest.mark.parametrize("X,Y,Z", FILM_CASES)
+def test_film_kernel_matches_oracle(isf, X, Y, Z):
+    """Many sweeps per launch from LDS, the books kept in the kernel: records of every step
+    (discards, a step of one sweep, a frozen one) and the spins equal the oracle's."""
+    h = _rand_h((Y, X), Z, 3 * X + Y + 13 * Z)
+    g, o = _pair(isf, h, Z, 0x5EED0F11, replica=5, init=2)
+    g.set_tuning(512, 1, 1, True, 4)
+    assert g.get_tuning()[4] == 4
+    _say("film kernel", X, Y, Z)
+    steps = [(2.5, 30, 66, 0), (0.8, -45, 4, 1), (9.0, 0, 3, 1), (4.0, -7, 5, 2), (1e-3, 241, 1, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps), np.array([o.run(*s).as_tuple() for s in steps]))
+    _assert_same(g, o)
+
+
+@pytest.mark.parametrize("X,Y,Z", [(64, 64, 3), (72, 38, 5)])
+def test_film_kernel_across_launch_chunks(isf, X, Y, Z):
+    """A step longer than one launch's sweeps (4096) and a schedule advanced in pieces that
+    end inside steps: the state carried from launch to launch through memory (both forms:
+    one dword of each sublattice per thread, and the lists of a sublattice of 513 dwords)."""
+    h = _rand_h((Y, X), Z, 99)
+    g, o = _pair(isf, h, Z, 4242, replica=1, init=0)
+    g.set_tuning(512, 1, 1, False, 4)
+    _say("film kernel, long step")
+    steps = [(3.5, 20, 4100, 100), (4.5, -20, 5000, 4097), (2.0, 0, 7, 0)]
+    np.testing.assert_array_equal(g.run_schedule(steps[:2]), np.array([o.run(*s).as_tuple() for s in steps[:2]]))
+    _assert_same(g, o, "long steps")
+    g2, o2 = _pair(isf, h, Z, 4242, replica=1, init=0)
+    g2.set_tuning(512, 1, 1, False, 4)
+    g2.schedule_load(steps)
+    done = 0
+    while g2.remaining():
+        done += g2.advance(1013)
+    assert done == sum(s[2] for s in steps)
+    np.testing.assert_array_equal(g2.records(), np.array([o2.run(*s).as_tuple() for s in steps]))
+    _assert_same(g2, o2, "advanced in pieces")
+
+
+def test_film_kernel_degenerate_films(isf):
+    _say("film kernel degenerate")
+    for h, Z in ((np.zeros((24, 64), dtype=np.uint8), 3), (np.full((24, 64), 4, dtype=np.uint8), 4),
+                 (np.ones((40, 32), dtype=np.uint8), 1)):
+        g, o = _pair(isf, h, Z, 5, init=2)
+        g.set_tuning(512, 1, 1, False, 4)
+        np.testing.assert_array_equal(g.run_sweeps(2.2, 10, 9, 3), o.run(2.2, 10, 9, 3).as_tuple())
+        _assert_same(g, o)
+
+
+def test_film_kernel_refusals(isf):
+    """Shapes and films the film kernel does not take are refused, and a refused tuning
+    leaves the film's own tuning in place."""
+    from paper_1205_5588_amd._lib import IsfError
+
+    _say("film kernel refusals")
+    g = isf.Lattice(_rand_h((128, 256), 5, 1), 5, 1)  # (Z + 2) Y X / 8 dwords and lists above the LDS
+    before = g.get_tuning()
+    with pytest.raises(IsfError):
+        g.set_tuning(512, 1, 1, True, 4)
+    assert g.get_tuning() == before
+    big = isf.Lattice(_rand_h((256, 2048), 1, 1), 1, 1)  # 196608 dwords: beyond 16-bit indices
+    with pytest.raises(IsfError):
+        big.set_tuning(512, 1, 1, True, 4)
+    small = isf.Lattice(_rand_h((16, 64), 2, 1), 2, 1)
+    for bad in ((256, 1, 1), (512, 2, 1), (512, 1, 2)):
+        with pytest.raises(IsfError):
+            small.set_tuning(bad[0], bad[1], bad[2], True, 4)
+    bp = isf.Lattice(_rand_h((16, 64), 2, 1), 2, 1, fmt=1)
+    with pytest.raises(IsfError):
+        bp.set_tuning(512, 1, 1, True, 4)
+    small.set_tuning(512, 1, 1, True, 4)
+    with pytest.raises(IsfError):  # the anisotropy term
+        small.schedule_load([(2.0, 0, 3, 0, 0, 40)])
+    small.schedule_load([(2.0, 0, 3, 0)])
+    with pytest.raises(IsfError):  # many sweeps per launch: no per-launch timing
+        small.time_launches(3)
+    small.set_tuning(64, 4, 2, True, 0)
+    small.schedule_load([(2.0, 0, 3, 0, 0, 40)])
+    with pytest.raises(IsfError):
+        small.set_tuning(512, 1, 1, True, 4)
+    for lat in (g, big, small, bp):
+        lat.close()
+
+
 def test_pipe_kernel_more_tiles_than_blocks_hold(isf):
     """A film with more tiles than the blocks of one per compute unit may take
     (32 x 16 tiles, 9600 of them): the grid grows instead."""
@@ -674,7 +763,7 @@ GATED_STEPS = [(2.5, 30, 7, 0, 40), (0.8, -45, 4, 1, 160), (9.0, 0, 5, 2, -20), 
 
 
 @pytest.mark.parametrize("kernel,tiling", [(0, (64, 4, 2)), (0, (16, 16, 1)), (1, (64, 4, 1)), (2, (32, 16, 8)),
-                                           (2, (16, 16, 4)), (3, (32, 16, 16))])
+                                           (2, (16, 16, 4)), (3, (32, 16, 16)), (4, (512, 1, 1))])
 @pytest.mark.parametrize("X,Y,Z", [(72, 38, 5), (328, 46, 6), (8, 4, 1), (352, 46, 6)])
 def test_gated_schedule_matches_oracle(isf, kernel, tiling, X, Y, Z):
     if kernel == 3 and (X // 8 < tiling[0] + 8 or Y < tiling[1] + 8):
