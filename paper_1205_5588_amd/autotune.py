@@ -49,15 +49,26 @@ def default_tiling(X: int, fmt: int) -> Tuple[int, int, int]:
     return (16, 16, 2) if fmt == FORMAT_INT8 else (16, 16, 1)
 
 
+def film_resident(X: int, Y: int, Z: int) -> bool:
+    """True where the film kernel runs in its resident form: no sublattice has more
+    dwords than the kernel's 512 threads."""
+    return (Z + 1) // 2 * (Y // 2) * (X // 8) <= 512
+
+
 def default_tuning(X: int, Y: int, Z: int, fmt: int) -> tuple:
     """Heuristic (tile_x, tile_y, rows_or_waves, use_graph, kernel) for films not in the cache.
 
-    INT8 films whose planes fit a whole-sweep kernel's LDS take one (measured
-    on MI355X: the pipelined kernel with 32 x 32 tiles on wide films such as
-    2048^2 x 8; the single-tile kernel with 16 x 16 tiles on smaller films,
-    where the pipelined kernel's 32 x 8 tiles win on some (512^2 x 5 at T up to
-    12) and lose on others (the batched workload's films, hot replicas among
-    them), so the tuner decides); others take the sublattice tiles."""
+    Small INT8 films that the film kernel takes in its resident form run there
+    (one block, many sweeps per launch: 2.6 us per sweep of 64 x 64 x 3 on
+    MI355X, against 9.3 us for one launch per sweep).  Other INT8 films whose
+    planes fit a whole-sweep kernel's LDS take one (the pipelined kernel with
+    32 x 32 tiles on wide films such as 2048^2 x 8; the single-tile kernel with
+    16 x 16 tiles on smaller films, where the pipelined kernel's 32 x 8 tiles
+    win on some (512^2 x 5 at T up to 12) and lose on others (the batched
+    workload's films, hot replicas among them), so the tuner decides); others
+    take the sublattice tiles."""
+    if fmt == FORMAT_INT8 and film_resident(X, Y, Z):
+        return (512, 1, 1, False, KERNEL_FILM)
     if fmt == FORMAT_INT8 and Z <= 8:
         if X // 8 >= 256 and Y >= 512:
             return (32, 32, 16, True, KERNEL_PIPE)

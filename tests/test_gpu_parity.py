@@ -236,13 +236,16 @@ def test_field_reversal_symmetry_gpu(isf):
 
 
 # ------------------------------------------------------------------ full-size workloads
-def test_config_plain_hysteresis_small_full(isf):
+@pytest.mark.parametrize("tuning", [None, (512, 1, 1, False, 4)])
+def test_config_plain_hysteresis_small_full(isf, tuning):
+    """The whole 64 x 64 x 3 ramp (161 steps of 100 sweeps) on the default sublattice
+    kernels and on the film kernel (its default and the tuner's pick)."""
     from isf_workloads import config_plain_hysteresis_small
 
     c = config_plain_hysteresis_small()
     h = c.heights()
-    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init)
-    _say("c1 full ramp")
+    g, o = _pair(isf, h, c.Z, c.mc_seed, init=c.init, tuning=tuning)
+    _say("small ramp, whole", tuning)
     rg = g.ramp_field(c.T, c.h_nums, c.sweeps_per_step)
     ro = cpu.hysteresis(o, c.T, c.h_nums, c.sweeps_per_step)
     np.testing.assert_array_equal(rg, ro)

@@ -117,3 +117,19 @@ def test_gate_thresholds_equal_oracle(lib, oracle_lib):
     assert lib.isf_gate_threshold(1.0, 200001, ctypes.byref(out)) == -1
     assert lib.isf_gate_threshold(0.0, 40, ctypes.byref(out)) == -1
     assert lib.isf_gate_threshold(1.0, 40, None) == -1
+
+
+def test_default_tuning_takes_the_film_kernel_where_resident():
+    """Small INT8 films run on the film kernel by default only where every sublattice
+    fits one dword per thread (the kernel's 512 threads); bit-packed films never."""
+    from paper_1205_5588_amd._lib import FORMAT_BITPACK, FORMAT_INT8, KERNEL_FILM
+    from paper_1205_5588_amd.autotune import default_tuning, film_resident
+
+    assert film_resident(64, 64, 3)  # 2 planes x 32 rows x 8 dwords = 512
+    assert not film_resident(64, 66, 3)
+    assert not film_resident(72, 38, 5)  # 3 x 19 x 9 = 513
+    assert film_resident(512, 12, 1) and film_resident(8, 4, 1)
+    assert default_tuning(64, 64, 3, FORMAT_INT8) == (512, 1, 1, False, KERNEL_FILM)
+    assert default_tuning(64, 64, 3, FORMAT_BITPACK)[4] != KERNEL_FILM
+    assert default_tuning(2048, 2048, 8, FORMAT_INT8)[4] != KERNEL_FILM
+    assert default_tuning(72, 38, 5, FORMAT_INT8)[4] != KERNEL_FILM
