@@ -263,19 +263,40 @@ __device__ __forceinline__ uint32_t shift_bits(bool left, uint32_t cur, uint32_t
     return left ? ((cur << 1) | ((other >> eb) & 1u)) : ((cur >> 1) | ((other & 1u) << eb));
 }
 
-// 4-bit bit-sliced counter: add one bit per site (counts stay <= 12).
+// 4-bit bit-sliced count per site (counts stay <= 12): plane k holds bit k.
 struct Cnt4 {
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    __device__ __forceinline__ void add(uint32_t x) {
-        const uint32_t k0 = c0 & x;
-        c0 ^= x;
-        const uint32_t k1 = c1 & k0;
-        c1 ^= k0;
-        const uint32_t k2 = c2 & k1;
-        c2 ^= k1;
-        c3 ^= k2;
-    }
 };
+
+// Full adder on 32 sites at once: s = a + b + c mod 2, cy = the majority.
+__device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &cy) {
+    s = a ^ b ^ c;
+    cy = (a & b) | (c & (a ^ b));
+}
+
+// Count of the 12 one-bit inputs x[0..12) per site by a carry-save tree: a
+// full adder keeps the weighted sum of its inputs, so the four bits left at
+// weights 1, 2, 4 and 8 are the exact count (8 full and 2 half adders,
+// against 12 increments of a 4-bit counter).
+__device__ __forceinline__ Cnt4 count12(const uint32_t (&x)[12]) {
+    uint32_t s0, s1, s2, s3, c0, c1, c2, c3;
+    full_add(x[0], x[1], x[2], s0, c0);
+    full_add(x[3], x[4], x[5], s1, c1);
+    full_add(x[6], x[7], x[8], s2, c2);
+    full_add(x[9], x[10], x[11], s3, c3);
+    uint32_t t0, d0;  // weight 1: s0..s3
+    full_add(s0, s1, s2, t0, d0);
+    Cnt4 r;
+    r.c0 = t0 ^ s3;
+    const uint32_t d1 = t0 & s3;
+    uint32_t e0, f0, e1, f1;  // weight 2: c0..c3, d0, d1
+    full_add(c0, c1, c2, e0, f0);
+    full_add(c3, d0, d1, e1, f1);
+    r.c1 = e0 ^ e1;
+    const uint32_t f2 = e0 & e1;
+    full_add(f0, f1, f2, r.c2, r.c3);  // weight 4: f0, f1, f2
+    return r;
+}
 
 struct NbBits {
     uint32_t spin, occ;
@@ -298,21 +319,24 @@ __device__ __forceinline__ NbBits gather_bp(const uint32_t *P, uint32_t Y, uint3
     r.occ = self[nw + w];
     const uint32_t *sh_rows[4] = {row(p1, ym), row(p1, yp), row(p0, y), row(p2, y)};
     const uint32_t *st_rows[4] = {row(p0, ym), row(p0, yp), row(p2, ym), row(p2, yp)};
+    uint32_t up[12], vac[12];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t *q = sh_rows[k];
         const uint32_t s = q[w], so = q[wo], o = q[nw + w], oo = q[nw + wo];
-        r.up.add(s);
-        r.vac.add(~o);
-        r.up.add(shift_bits(left, s, so, eb));
-        r.vac.add(~shift_bits(left, o, oo, eb));
+        up[2 * k] = s;
+        vac[2 * k] = ~o;
+        up[2 * k + 1] = shift_bits(left, s, so, eb);
+        vac[2 * k + 1] = ~shift_bits(left, o, oo, eb);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t *q = st_rows[k];
-        r.up.add(q[w]);
-        r.vac.add(~q[nw + w]);
+        up[8 + k] = q[w];
+        vac[8 + k] = ~q[nw + w];
     }
+    r.up = count12(up);
+    r.vac = count12(vac);
     return r;
 }
 
@@ -400,12 +424,18 @@ __device__ __forceinline__ void phase_tile_bp_g(const LatDev &L, uint32_t sigma,
 #pragma unroll
             for (int p = 0; p < 6; ++p)
                 key |= ((((ix.b[p] >> (4 * g)) & 0xFu) * 0x00204081u) & 0x01010101u) << p;
+            // the four threshold reads are issued together and the vacancies
+            // masked afterwards (a read per site behind its occupancy test made
+            // four LDS round trips in a row); a vacant site's index is in the
+            // table too: 2U + D <= 24 since U + D <= 12, so idx <= 49
+            uint32_t thr[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t thr = tab[(key >> (8 * j)) & 0xFFu];
-                const bool ok = ((occ4 >> j) & 1u) && min(u[j], kSentinel - 1u) < thr;  // exact: see phase_block_i8
-                fg |= (uint32_t)ok << j;
-            }
+            for (int j = 0; j < 4; ++j)
+                thr[j] = tab[(key >> (8 * j)) & 0xFFu];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)  // exact: see phase_block_i8
+                fg |= (uint32_t)(min(u[j], kSentinel - 1u) < thr[j]) << j;
+            fg &= occ4;
             // the switching-field gate of Eq. (9): the group's own draw (tag 2),
             // needed only where a Metropolis test passed
             if (kGate && fg) {
