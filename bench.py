@@ -188,7 +188,7 @@ def alu_ceiling(lat, cfg, n_sweeps=200):
             "attempts_per_s": round(n_occ * n_sweeps / (ms * 1e-3), 1)}
 
 
-KERNEL_SOURCES = ("isf_sweep.hip", "isf_device.h", "isf_internal.h")
+KERNEL_SOURCES = ("isf_sweep.hip", "isf_books.h", "isf_device.h", "isf_internal.h")
 
 
 def measured_traffic(kernel):

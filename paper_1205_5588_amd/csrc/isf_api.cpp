@@ -61,7 +61,7 @@ uint64_t halo_lists_bytes_max(uint32_t nd, uint32_t Y, uint32_t Z);
 hipError_t launch_sweep_end_batch(const BatchEntry *ents_dev, uint32_t n_ents, hipStream_t s);
 hipError_t launch_recount_i8(const LatDev &L, int64_t *out, hipStream_t s);
 
-hipError_t launch_phase_bp(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s);
+hipError_t launch_phase_bp_pos(const LatDev &L, const Tiling &tl, uint32_t sigma, uint32_t q, hipStream_t s);
 hipError_t launch_phase_bp_batch(const BatchEntry *ents_dev, uint32_t n_ents, uint32_t total_blocks,
                                  const Tiling &tl, uint32_t sigma, hipStream_t s);
 void batch_grid_bp(const LatDev &L, const Tiling &tl, uint32_t &nbx, uint32_t &nby, uint32_t &nbz);
@@ -238,6 +238,10 @@ struct isf_lattice {
     // a run of whole-sweep launches is open: the schedule position lives in the
     // parity-buffered positions until k_whole_flush hands it back
     bool whole_active;
+    // parity of the next sweep of a bit-packed film, whose per-sublattice
+    // launches carry their books as the whole-sweep kernels do (the INT8
+    // whole-sweep kernels take theirs from cur_spare)
+    uint32_t bq;
     // the loaded schedule has the anisotropy term (also in L.aniso, which the
     // phase kernels read)
     bool aniso;
@@ -273,6 +277,14 @@ struct isf_batch {
 
 namespace {
 
+// Launches that carry their sweep's books (positions and slots by sweep
+// parity, opened by k_whole_prime and closed by k_whole_flush): the whole-sweep
+// kernels, and the per-sublattice launches of a bit-packed film, whose first
+// sublattice folds the sweep before it.
+bool books_bp(const isf_lattice *lat) { return lat->d.format == ISF_FORMAT_BITPACK; }
+bool books_in_launch(const isf_lattice *lat) { return is_whole(lat->tiling.kernel) || books_bp(lat); }
+uint32_t run_parity(const isf_lattice *lat) { return books_bp(lat) ? lat->bq : (lat->cur_spare ? 1u : 0u); }
+
 int32_t set_device_of(const isf_lattice *lat) {
     HIP_TRY(hipSetDevice(lat->device));
     return ISF_OK;
@@ -285,13 +297,20 @@ int32_t launch_phase(const isf_lattice *lat, uint32_t sigma) {
     else if (lat->d.format == ISF_FORMAT_INT8)
         e = launch_phase_i8(lat->L, lat->tiling, sigma, lat->stream);
     else
-        e = launch_phase_bp(lat->L, lat->tiling, sigma, lat->stream);
+        e = launch_phase_bp_pos(lat->L, lat->tiling, sigma, lat->bq, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "phase launch failed: %s", hipGetErrorString(e));
     return ISF_OK;
 }
 
-int32_t launch_end(const isf_lattice *lat) {
+// After a sweep's four sublattice launches: the one-wave sweep end, or for a
+// bit-packed film (whose next sweep's first launch folds this one) the flip of
+// the sweep parity.
+int32_t launch_end(isf_lattice *lat) {
+    if (books_bp(lat)) {
+        lat->bq ^= 1u;
+        return ISF_OK;
+    }
     hipError_t e = launch_sweep_end(lat->L, lat->stream);
     if (e != hipSuccess)
         return fail(ISF_EHIP, "sweep-end launch failed: %s", hipGetErrorString(e));
@@ -331,7 +350,7 @@ int32_t prepare_spare(isf_lattice *lat, const Tiling &tl, uint32_t cap = 0) {
 // Open a run of whole-sweep launches (before the first one is enqueued or captured).
 int32_t prime_whole(isf_lattice *lat) {
     if (!lat->whole_active) {
-        hipError_t e = launch_whole_prime(lat->L, lat->cur_spare ? 1u : 0u, lat->stream);
+        hipError_t e = launch_whole_prime(lat->L, run_parity(lat), lat->stream);
         if (e == hipSuccess && lat->lists_ready && lat->lists_tiling.kernel == ISF_KERNEL_PIPE)
             e = launch_pipe_reset(lat->L, lat->lists_tiling, lat->lists, lat->stream);
         if (e != hipSuccess)
@@ -370,7 +389,7 @@ int32_t pipe_fits(const isf_lattice *lat, const Tiling &tl, uint32_t Zlds, bool 
 // Close the run: fold the last sweep, whose parity is the opposite of the next one's.
 int32_t flush_whole(isf_lattice *lat) {
     if (lat->whole_active) {
-        hipError_t e = launch_whole_flush(lat->L, lat->cur_spare ? 0u : 1u, lat->stream);
+        hipError_t e = launch_whole_flush(lat->L, 1u - run_parity(lat), lat->stream);
         if (e != hipSuccess)
             return fail(ISF_EHIP, "flush launch failed: %s", hipGetErrorString(e));
         lat->whole_active = false;
@@ -520,11 +539,12 @@ int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     int32_t rc0;
     if (lat->tiling.kernel == ISF_KERNEL_FILM)
         return enqueue_sweeps_film(lat, n);
-    if (is_whole(lat->tiling.kernel)) {
-        if ((rc0 = prepare_spare(lat, lat->tiling)) || (rc0 = prime_whole(lat)))
+    if (books_in_launch(lat)) {
+        if ((is_whole(lat->tiling.kernel) && (rc0 = prepare_spare(lat, lat->tiling))) || (rc0 = prime_whole(lat)))
             return rc0;
-        // graphs hold an even number of whole sweeps and start from the main copy
-        if (lat->cur_spare && n > 0) {
+        // graphs hold an even number of sweeps and start at parity 0 (for the
+        // whole-sweep kernels: from the main copy)
+        if (run_parity(lat) && n > 0) {
             if ((rc0 = enqueue_sweeps_plain(lat, 1)))
                 return rc0;
             --n;
@@ -545,7 +565,7 @@ int32_t enqueue_sweeps(isf_lattice *lat, uint64_t n) {
     }
     // the remainder: a graph of exactly that many sweeps, cached for the next
     // request of the same length (whole-sweep graphs need an even count)
-    if (lat->use_graph && lat->stream && n >= kTailGraphMin && (n % 2 == 0 || !is_whole(lat->tiling.kernel))) {
+    if (lat->use_graph && lat->stream && n >= kTailGraphMin && (n % 2 == 0 || !books_in_launch(lat))) {
         if (!lat->tail_graph || lat->tail_sweeps != n || !same_tiling(lat->tail_tiling, lat->tiling)) {
             int32_t rc = build_tail_graph(lat, (uint32_t)n);
             if (rc)
@@ -1501,7 +1521,8 @@ int32_t isf_time_launches(isf_lattice *lat, uint32_t n_sweeps, double ms[4], uin
         HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     int32_t status = ISF_OK;
     const bool whole = is_whole(lat->tiling.kernel);
-    if (whole ? ((rc = prepare_spare(lat, lat->tiling)) || (rc = prime_whole(lat))) : (rc = settle(lat)) != 0) {
+    if (books_in_launch(lat) ? ((whole && (rc = prepare_spare(lat, lat->tiling))) || (rc = prime_whole(lat)))
+                             : (rc = settle(lat)) != 0) {
         for (auto &e : ev)
             (void)hipEventDestroy(e);
         return rc;

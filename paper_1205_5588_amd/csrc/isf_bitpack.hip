@@ -16,20 +16,10 @@
 
 #include <algorithm>
 
+#include "isf_books.h"
 #include "isf_tiles.h"
 
 namespace isf {
-
-template <int TX, int TY, int RY>
-__global__ __launch_bounds__(TX *TY) void k_phase_bp(LatDev L, uint32_t sigma) {
-    __shared__ uint32_t tab[kTableWords];
-    __shared__ uint32_t t_sh, run_sh;
-    stage_film<false>(L, tab, &t_sh, &run_sh);
-    int dM = 0, dE = 0, acc = 0;
-    phase_tile_bp<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
-    const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    finish_block<TX * TY>(L, dM, dE, acc, blin);
-}
 
 template <int TX, int TY, int RY>
 __global__ __launch_bounds__(TX *TY) void k_phase_bp_batch(const BatchEntry *__restrict__ ents, uint32_t n_ents,
@@ -47,6 +37,44 @@ __global__ __launch_bounds__(TX *TY) void k_phase_bp_batch(const BatchEntry *__r
     int dM = 0, dE = 0, acc = 0;
     phase_tile_bp<TX, TY, RY>(L, sigma, bx, by, bz, tab, t_sh, dM, dE, acc);
     finish_block<TX * TY>(L, dM, dE, acc, bl);
+}
+
+// One sublattice of a sweep of parity q whose books ride in the launches (as
+// the whole-sweep kernels keep them): the thresholds, sweep counter and run
+// flag come from pos[q], the block sums go to slots_of(q), and in the first
+// sublattice wave 0 of block 0 folds the sweep before (parity 1 - q) into the
+// film state and its record and writes the next sweep's position.  This saves
+// the one-wave sweep-end launch of every sweep.
+template <int TX, int TY, int RY>
+__global__ __launch_bounds__(TX *TY) void k_phase_bp_pos(LatDev L, uint32_t sigma, uint32_t q) {
+    __shared__ uint32_t tab[kTableWords];
+    __shared__ uint32_t t_sh, run_sh;
+    __shared__ BookLds bk;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t blin = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const bool booker = sigma == 0 && blin == 0 && tid < 64;  // uniform per wave
+    BookRegs br{};
+    if (booker)
+        br = book_issue(L, 1 - q, q, tid);
+    const SweepPos &P = L.pos[q];
+    if (tid < kTableWords)
+        tab[tid] = P.table[tid];
+    if (tid == 0) {
+        t_sh = (uint32_t)P.t;
+        run_sh = P.run;
+    }
+    if (booker)
+        book_stage(bk, br, tid);
+    __syncthreads();
+    if (booker) {
+        book_fold(L, 1 - q, bk, tid);
+        book_advance(L, q, bk, tab, tid);
+    }
+    if (!run_sh)  // uniform: the schedule is finished; nothing flips
+        return;
+    int dM = 0, dE = 0, acc = 0;
+    phase_tile_bp<TX, TY, RY>(L, sigma, blockIdx.x, blockIdx.y, blockIdx.z, tab, t_sh, dM, dE, acc);
+    finish_block_to<TX * TY>(slots_of(L, q), dM, dE, acc, blin);
 }
 
 // Start: spin bit 1 on occupied sites for UP, 0 for DOWN, draw < 2^31 for RANDOM.
@@ -114,13 +142,13 @@ static void grid_bp(const LatDev &L, const Tiling &tl, dim3 &g) {
     g.z = (L.Z + 1) / 2;
 }
 
-hipError_t launch_phase_bp(const LatDev &L, const Tiling &tl, uint32_t sigma, hipStream_t s) {
+hipError_t launch_phase_bp_pos(const LatDev &L, const Tiling &tl, uint32_t sigma, uint32_t q, hipStream_t s) {
     dim3 g;
     grid_bp(L, tl, g);
-#define X(a, b, c)                                                                  \
-    if (tl.tx == a && tl.ty == b && tl.ry == c) {                                   \
-        hipLaunchKernelGGL((k_phase_bp<a, b, c>), g, dim3(a * b), 0, s, L, sigma); \
-        return hipGetLastError();                                                   \
+#define X(a, b, c)                                                                         \
+    if (tl.tx == a && tl.ty == b && tl.ry == c) {                                          \
+        hipLaunchKernelGGL((k_phase_bp_pos<a, b, c>), g, dim3(a * b), 0, s, L, sigma, q); \
+        return hipGetLastError();                                                          \
     }
     ISF_BP_TILINGS(X)
 #undef X
