@@ -27,7 +27,7 @@ TILINGS = {
     FORMAT_INT8: [(64, 4, 1), (64, 4, 2), (64, 4, 4), (32, 8, 1), (32, 8, 2), (32, 8, 4), (16, 16, 1), (16, 16, 2),
                   (16, 16, 4)],
     FORMAT_BITPACK: [(64, 4, 1), (64, 4, 2), (32, 8, 1), (32, 8, 2), (16, 16, 1), (16, 16, 2), (8, 32, 1), (8, 32, 2),
-                     (8, 16, 1)],
+                     (8, 16, 1), (8, 8, 1)],
 }
 
 GRAPH_SWEEPS = 64  # sweeps per captured graph in the library
@@ -168,11 +168,11 @@ def tune_lattice(make: Callable[[], "object"], fmt: int, T: float, h_num: int, s
 # that of the films the pipelined kernel cannot take (sublattice launches)
 # Sublattice shapes of both formats (a shape the format does not compile is
 # refused and skipped): on batches of small films the narrow bit-packed tiles
-# (8 or 16 words, 256 or 512 sites of a row per tile) and the int8 tiles with
+# (8 or 16 words, 256 or 512 sites of a row per tile, one to four waves) and the int8 tiles with
 # four rows per thread lead.
 BATCH_CANDIDATES = [(64, 4, 2, BATCH_PHASE_LAUNCH), (64, 4, 4, BATCH_PHASE_LAUNCH), (32, 8, 2, BATCH_PHASE_LAUNCH),
                     (32, 8, 4, BATCH_PHASE_LAUNCH), (16, 16, 1, BATCH_PHASE_LAUNCH), (16, 16, 2, BATCH_PHASE_LAUNCH),
-                    (8, 32, 1, BATCH_PHASE_LAUNCH), (8, 16, 1, BATCH_PHASE_LAUNCH),
+                    (8, 32, 1, BATCH_PHASE_LAUNCH), (8, 16, 1, BATCH_PHASE_LAUNCH), (8, 8, 1, BATCH_PHASE_LAUNCH),
                     (64, 4, 2, BATCH_PERSISTENT), (16, 16, 4, BATCH_WHOLE), (32, 8, 4, BATCH_WHOLE),
                     (32, 16, 8, BATCH_WHOLE), (64, 4, 2, BATCH_PIPE), (32, 8, 2, BATCH_PIPE)]
 

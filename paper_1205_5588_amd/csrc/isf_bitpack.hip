@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_recount_bp(LatDev L, int64_t *out) {
 }
 
 #define ISF_BP_TILINGS(X) \
-    X(64, 4, 1) X(64, 4, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) X(16, 16, 2) X(8, 32, 1) X(8, 32, 2) X(8, 16, 1)
+    X(64, 4, 1) X(64, 4, 2) X(32, 8, 1) X(32, 8, 2) X(16, 16, 1) X(16, 16, 2) X(8, 32, 1) X(8, 32, 2) X(8, 16, 1) X(8, 8, 1)
 
 static void grid_bp(const LatDev &L, const Tiling &tl, dim3 &g) {
     g.x = (L.nd + tl.tx - 1) / tl.tx;

@@ -110,7 +110,7 @@ def test_bitpack_matches_oracle(isf, tiling):
 BP_PARTIAL = [(8, 4, 2), (72, 10, 3), (88, 26, 4), (120, 12, 5), (1000, 6, 2)]
 
 
-@pytest.mark.parametrize("tiling", [(64, 4, 1), (32, 8, 2), (16, 16, 1), (8, 32, 1), (8, 16, 1)])
+@pytest.mark.parametrize("tiling", [(64, 4, 1), (32, 8, 2), (16, 16, 1), (8, 32, 1), (8, 16, 1), (8, 8, 1)])
 @pytest.mark.parametrize("X,Y,Z", BP_PARTIAL)
 def test_bitpack_partial_words_match_oracle_and_int8(isf, tiling, X, Y, Z):
     h = _rand_h((Y, X), Z, 3 * X + Y)
